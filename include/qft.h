@@ -1,0 +1,137 @@
+/*
+ * qft.h - C ABI of the MI355X (gfx950) improved-QFT DFT library.
+ *
+ * The library computes, for complex signals x of length N = 2^r (r >= 1),
+ *
+ *     X(k) = sum_{n=0}^{N-1} x(n) exp(-2*pi*i*n*k/N),   k = 0..N-1
+ *
+ * unnormalised, in natural order (Pasquini, "Improved QFT algorithm for
+ * power-of-two FFT", Sec. 2.1, eq. qft_0A with theta = 2*pi/N, eq. qft_0D),
+ * by the improved Quick Fourier Transform of Sec. 5: the real/imaginary split
+ * and real fold of Sec. 4.1-4.2, the DCT-0/DST-0 recursion with the extra
+ * even/odd time-index decomposition of Sec. 5.2, and the secant conversion
+ * (eq. qft_38A) applied only to odd-time/odd-harmonic signals.  All
+ * arithmetic on the GPU is FP32; the N/4 trigonometric constants of Sec. 6.1
+ * are generated on the host in FP64 and rounded once to FP32.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Data layout: transform-major and contiguous.  For a uniform plan element
+ *    (b, n) lives at element offset b*N + n.  For an uneven plan transform i
+ *    starts at the exclusive prefix sum of 2^log2n[j], j < i.
+ *  - Element types: QFT_C32 = interleaved {float re, im} (8 bytes);
+ *    QFT_C16 = interleaved {_Float16 re, im} (4 bytes, IEEE binary16),
+ *    converted to FP32 on load and rounded to nearest-even on store.
+ *  - Pointers passed to exec are DEVICE pointers on the plan's device.  The
+ *    caller owns them.  `in` is only written when in == out (in-place);
+ *    any other overlap of the two ranges is rejected.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  exec is
+ *    asynchronous and stream-ordered; it never synchronises and never
+ *    allocates device memory, so it may be captured in a HIP graph.
+ *  - One exec may be in flight per plan at a time (the plan owns scratch
+ *    memory); different plans may run concurrently.
+ *  - Errors are returned as status codes, never by abort.  Arguments are
+ *    validated before any HIP call, so invalid calls have no side effects.
+ */
+#ifndef QFT_H
+#define QFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qft_plan_s* qft_plan_t;
+
+typedef enum {
+    QFT_SUCCESS = 0,
+    QFT_ERROR_INVALID_VALUE = 1, /* null pointer, batch/count <= 0, bad dtype */
+    QFT_ERROR_INVALID_SIZE = 2,  /* log2n outside [1, QFT_MAX_LOG2N] */
+    QFT_ERROR_ALIGNMENT = 3,     /* pointer not aligned to the element size */
+    QFT_ERROR_OVERLAP = 4,       /* in/out partially overlap */
+    QFT_ERROR_ALLOC = 5,         /* device or host allocation failed */
+    QFT_ERROR_HIP = 6,           /* a HIP runtime call failed: qft_last_hip_error() */
+    QFT_ERROR_UNSUPPORTED = 7    /* device is not gfx950 / feature not built */
+} qft_status;
+
+typedef enum {
+    QFT_C32 = 0, /* complex FP32 storage, FP32 compute */
+    QFT_C16 = 1  /* complex FP16 storage, FP32 compute */
+} qft_dtype;
+
+#define QFT_MAX_LOG2N 24
+
+/*
+ * Plan for `batch` transforms of length N = 2^log2n each (Sec. 2.1 problem
+ * statement).  Allocates the device constant table (Sec. 6.1: N/4 constants,
+ * the secants 1/(2 cos(2*pi*q/N)) of eq. qft_38A and cos(2*pi/8)) and, for N
+ * beyond one workgroup's local memory, a device scratch of 2*batch*N complex
+ * FP32 values.  `device` is a HIP device ordinal.  On success *plan receives
+ * a handle owned by the caller (free with qft_plan_destroy); on failure
+ * *plan is set to NULL.
+ */
+qft_status qft_plan_create(qft_plan_t* plan, int log2n, int64_t batch, qft_dtype dtype,
+                           int device);
+
+/*
+ * Plan for `count` transforms of possibly different lengths 2^log2n[i]
+ * (host array, read during the call only), packed back to back in the given
+ * order.  Every log2n[i] must lie in [1, QFT_MAX_LOG2N]; transforms longer
+ * than one workgroup's local memory are handled by the multi-pass path.  The
+ * plan builds a size-sorted work list and runs all transforms that fit in
+ * local memory in one persistent launch.
+ */
+qft_status qft_plan_create_uneven(qft_plan_t* plan, const int32_t* log2n, int64_t count,
+                                  qft_dtype dtype, int device);
+
+/* X = F x: forward transform of every signal of the plan (eq. qft_0A). */
+qft_status qft_exec_fwd(qft_plan_t plan, const void* in, void* out, void* stream);
+
+/*
+ * x = F^H X: the adjoint (conjugate transpose), exp(+2*pi*i*n*k/N), also
+ * unnormalised, so exec_bwd(exec_fwd(x)) = N x.  It runs the same improved-QFT
+ * plan on swap(X) and swaps the result, swap(a + ib) = b + ia, since
+ * F^H g = swap(F swap(g)).
+ */
+qft_status qft_exec_bwd(qft_plan_t plan, const void* in, void* out, void* stream);
+
+/* Frees every device and host resource of the plan.  NULL is accepted. */
+qft_status qft_plan_destroy(qft_plan_t plan);
+
+/*
+ * Plan figures (any output pointer may be NULL):
+ *   total_points  sum of N over the plan's transforms;
+ *   algo_bytes    bytes one exec must move at minimum (read + write of every
+ *                 element once: 2 * total_points * element size);
+ *   flops_5nlogn  sum of 5 N log2 N (the usual FFT flop convention);
+ *   flops_actual  sum of 4 N log2 N - 6N + 8, the improved QFT's real
+ *                 additions plus multiplications (Table 2, CDFT row).
+ */
+qft_status qft_plan_info(qft_plan_t plan, int64_t* total_points, int64_t* algo_bytes,
+                         double* flops_5nlogn, double* flops_actual);
+
+/*
+ * Host-only (no GPU needed): writes the FP32 constant table used for
+ * transforms up to N = 2^log2n_max into out[0 .. N/4 - 1].  Entry L + m,
+ * for L = 1, 2, 4, .., N/8 and 0 <= m < L, is
+ *     1 / (2 cos(pi (2m + 1) / (4L)))
+ * (the secant 1/(2 cos(theta n)) of eq. qft_38A with theta = 2*pi/(8L) and
+ * odd n = 2m + 1), evaluated in FP64 as 1 / (2 sin(pi (2L - 2m - 1) / (4L)))
+ * and rounded once to FP32.  out[0] is 0 (unused).  Entry 1 is
+ * 1/(2 cos(pi/4)) = cos(pi/4), the extra constant of Sec. 6.1.
+ * Requires 3 <= log2n_max <= QFT_MAX_LOG2N.
+ */
+qft_status qft_secant_table(float* out, int log2n_max);
+
+/* Static description of a status code. */
+const char* qft_status_string(qft_status s);
+
+/* The hipError_t value of the last QFT_ERROR_HIP on this thread (0 if none). */
+int qft_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QFT_H */

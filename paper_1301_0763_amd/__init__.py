@@ -1,0 +1,160 @@
+"""Improved-QFT power-of-two DFT on MI355X (gfx950).
+
+Python face of the C ABI in include/qft.h.  PyTorch is used only for device
+memory and streams: tensors are handed to the library as raw device pointers
+on torch's current HIP stream, and every arithmetic step runs in the library's
+gfx950 kernels.
+
+    X = fft(x)              # X(k) = sum_n x(n) exp(-2 pi i n k / N), last axis
+    x = fft_adjoint(X)      # conjugate transpose, unnormalised
+    X = QFTFunction.apply(x)            # differentiable (backward = adjoint)
+    Y = fft_packed(values, log2n_list)  # uneven batch, one persistent launch
+
+Supported storage: complex64 (FP32) and complex32 / torch.chalf (FP16 storage,
+FP32 arithmetic).  N = 2^r with 1 <= r <= 24.
+"""
+import threading
+
+from . import _lib
+from ._lib import (QFT_C16, QFT_C32, QFT_MAX_LOG2N, QFTError, qft_exec_bwd, qft_exec_fwd,
+                   qft_last_hip_error, qft_plan_create, qft_plan_create_uneven,
+                   qft_plan_destroy, qft_plan_info, qft_secant_table, qft_status_string)
+
+__all__ = [
+    "Plan", "UnevenPlan", "fft", "fft_adjoint", "fft_packed", "QFTFunction", "QFTError",
+    "qft_plan_create", "qft_plan_create_uneven", "qft_exec_fwd", "qft_exec_bwd",
+    "qft_plan_destroy", "qft_plan_info", "qft_secant_table", "qft_status_string",
+    "qft_last_hip_error", "QFT_C32", "QFT_C16", "QFT_MAX_LOG2N",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.complex64:
+        return QFT_C32
+    if t.dtype == torch.complex32:
+        return QFT_C16
+    raise TypeError(f"unsupported dtype {t.dtype}; use complex64 or complex32")
+
+
+def _log2n(N):
+    r = int(N).bit_length() - 1
+    if N < 2 or (1 << r) != N:
+        raise ValueError(f"transform length {N} is not a power of two >= 2")
+    return r
+
+
+def _stream_ptr(device):
+    return _torch().cuda.current_stream(device).cuda_stream
+
+
+class Plan:
+    """Plan for `batch` transforms of length 2^log2n (qft_plan_create)."""
+
+    def __init__(self, log2n, batch, dtype=QFT_C32, device=0):
+        self.log2n, self.batch, self.dtype, self.device = int(log2n), int(batch), dtype, device
+        self.handle = qft_plan_create(log2n, batch, dtype, device)
+        self.info = qft_plan_info(self.handle)
+
+    def _check(self, x, y):
+        if not (x.is_cuda and y.is_cuda):
+            raise ValueError("tensors must be on the GPU")
+        if not (x.is_contiguous() and y.is_contiguous()):
+            raise ValueError("tensors must be contiguous")
+        if x.numel() != self.info["total_points"] or y.numel() != self.info["total_points"]:
+            raise ValueError("tensor size does not match the plan")
+        if _dtype_code(x) != self.dtype or _dtype_code(y) != self.dtype:
+            raise ValueError("tensor dtype does not match the plan")
+
+    def forward(self, x, out=None):
+        torch = _torch()
+        out = torch.empty_like(x) if out is None else out
+        self._check(x, out)
+        qft_exec_fwd(self.handle, x.data_ptr(), out.data_ptr(), _stream_ptr(x.device))
+        return out
+
+    def adjoint(self, X, out=None):
+        torch = _torch()
+        out = torch.empty_like(X) if out is None else out
+        self._check(X, out)
+        qft_exec_bwd(self.handle, X.data_ptr(), out.data_ptr(), _stream_ptr(X.device))
+        return out
+
+    def close(self):
+        if self.handle:
+            qft_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class UnevenPlan(Plan):
+    """Plan for transforms of lengths 2^log2n[i] packed back to back."""
+
+    def __init__(self, log2n_list, dtype=QFT_C32, device=0):
+        self.log2n_list = [int(v) for v in log2n_list]
+        self.dtype, self.device = dtype, device
+        self.handle = qft_plan_create_uneven(self.log2n_list, dtype, device)
+        self.info = qft_plan_info(self.handle)
+
+
+_cache = {}
+_cache_lock = threading.Lock()
+
+
+def _plan_for(x):
+    N = x.shape[-1]
+    log2n = _log2n(N)
+    batch = x.numel() // N
+    dev = x.device.index if x.device.index is not None else _torch().cuda.current_device()
+    key = (log2n, batch, _dtype_code(x), dev)
+    with _cache_lock:
+        p = _cache.get(key)
+        if p is None:
+            p = Plan(log2n, batch, key[2], dev)
+            _cache[key] = p
+    return p
+
+
+def fft(x):
+    """Forward unnormalised DFT of the last axis of a complex GPU tensor."""
+    x = x.contiguous()
+    return _plan_for(x).forward(x)
+
+
+def fft_adjoint(X):
+    """Adjoint (conjugate-transpose) DFT of the last axis: fft_adjoint(fft(x)) = N x."""
+    X = X.contiguous()
+    return _plan_for(X).adjoint(X)
+
+
+def fft_packed(values, log2n_list, plan=None):
+    """Forward DFTs of an uneven batch packed back to back in a 1-D tensor."""
+    values = values.contiguous()
+    if plan is None:
+        dev = values.device.index if values.device.index is not None else 0
+        plan = UnevenPlan(log2n_list, _dtype_code(values), dev)
+    return plan.forward(values)
+
+
+class QFTFunction(_torch().autograd.Function):
+    """X = F x with backward F^H g (PyTorch's convention for C -> C maps: the
+    vector-Jacobian product of a linear map is its adjoint), both through the
+    same improved-QFT plan."""
+
+    @staticmethod
+    def forward(ctx, x):
+        return fft(x)
+
+    @staticmethod
+    def backward(ctx, g):
+        return fft_adjoint(g.contiguous())

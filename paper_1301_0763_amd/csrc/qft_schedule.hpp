@@ -1,0 +1,104 @@
+// Host-side schedules of the improved-QFT library, shared by the GPU launcher
+// (qft_lib.hip) and the CPU emulation used by the tests, so both run the very
+// same sequence of passes.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+namespace qftk {
+
+// Constant table for transforms up to N = 2^log2n_max (N/4 entries, Sec. 6.1):
+// entry L + m (L = 1, 2, 4, .., N/8; m < L) = 1/(2 cos(pi (2m+1)/(4L))), the
+// secant 1/(2 cos(theta n)) of eq. qft_38A for the periodization 8L and odd
+// n = 2m+1.  Evaluated in FP64 through the complement angle,
+// 1/(2 sin(pi (2L-2m-1)/(4L))), so the argument never approaches the zero of
+// the cosine, and rounded once to FP32.  out[0] is unused (0).
+inline void fill_secants(float* out, int log2n_max) {
+  const int64_t nt = ((int64_t)1 << log2n_max) / 4;
+  out[0] = 0.0f;
+  for (int64_t L = 1; 2 * L <= nt; L *= 2) {
+    for (int64_t m = 0; m < L; ++m) {
+      const double a = M_PI * (double)(2 * L - 2 * m - 1) / (double)(4 * L);
+      out[L + m] = (float)(1.0 / (2.0 * std::sin(a)));
+    }
+  }
+}
+
+// Multi-pass schedule for transforms of length 2^logn that do not fit one
+// workgroup, with LDS segments of 2^seg_log2 cells (logn >= seg_log2 + 3).
+// `ex` provides: fold(), fwd(K, hi), segment(), bwd(s) (returns nothing; the
+// executor swaps its ping-pong buffers), chain(p), combine().
+//
+//   fold                 x -> heap buffer (real fold, Sec. 4.2)
+//   fwd(K, hi)           forward rounds S = 2^hi .. 2^(hi-K+1) on the blocks
+//                        longer than one segment (rounds S > 2^seg_log2)
+//   segment              every 2^seg_log2 segment: its remaining forward
+//                        rounds and its backward rounds in LDS; the core
+//                        (both side heads) also runs the chain to
+//                        P = 2^(seg_log2+1)
+//   bwd(s)               backward round S = 2^s > 2^seg_log2
+//   chain(p)             chain level P = 2^p > 2^(seg_log2+1)
+//   combine              heap buffer -> X (Sec. 4.1 combine)
+template <class Exec>
+void multipass_schedule(Exec& ex, int logn, int seg_log2) {
+  ex.fold();
+  const int top = logn - 2, bottom = seg_log2 + 1;
+  if (top >= bottom) {
+    const int R = top - bottom + 1;
+    const int nch = (R + 2) / 3;
+    for (int c = nch - 1; c >= 0; --c) {
+      const int lo = bottom + 3 * c;
+      const int hi = std::min(top, lo + 2);
+      ex.fwd(hi - lo + 1, hi);
+    }
+  }
+  ex.segment();
+  for (int s = seg_log2 + 1; s <= logn - 2; ++s) ex.bwd(s);
+  for (int p = seg_log2 + 2; p <= logn; ++p) ex.chain(p);
+  ex.combine();
+}
+
+struct TileDesc {
+  int log2n;
+  int first;  // index into the permuted offset list
+  int count;
+};
+
+// Work list of an uneven plan.  Transforms with log2n <= tile_log2 are grouped
+// by size, largest size first, into tiles of at most 2^(tile_log2 - log2n)
+// transforms; `perm` lists their element offsets tile by tile.  Longer
+// transforms go to `large` (index, largest first).  `offsets` receives the
+// packed layout (exclusive prefix sum of 2^log2n[i]).
+inline void build_uneven_worklist(const int32_t* log2n, int64_t count, int tile_log2,
+                                  std::vector<int64_t>& offsets, std::vector<TileDesc>& tiles,
+                                  std::vector<int64_t>& perm, std::vector<int64_t>& large) {
+  offsets.assign(count, 0);
+  int64_t acc = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    offsets[i] = acc;
+    acc += (int64_t)1 << log2n[i];
+  }
+  tiles.clear();
+  perm.clear();
+  large.clear();
+  std::vector<std::vector<int64_t>> cls(tile_log2 + 1);
+  for (int64_t i = 0; i < count; ++i) {
+    if (log2n[i] <= tile_log2) cls[log2n[i]].push_back(offsets[i]);
+    else large.push_back(i);
+  }
+  for (int lg = tile_log2; lg >= 1; --lg) {
+    const size_t per_tile = (size_t)1 << (tile_log2 - lg);
+    for (size_t a = 0; a < cls[lg].size(); a += per_tile) {
+      const int cnt = (int)std::min(per_tile, cls[lg].size() - a);
+      tiles.push_back({lg, (int)perm.size(), cnt});
+      for (int q = 0; q < cnt; ++q) perm.push_back(cls[lg][a + q]);
+    }
+  }
+  std::stable_sort(large.begin(), large.end(),
+                   [&](int64_t a, int64_t b) { return log2n[a] > log2n[b]; });
+}
+
+}  // namespace qftk

@@ -1,0 +1,43 @@
+"""Builds the CPU emulation of the GPU kernels (tests/emu/libqft_emu.so).
+
+Host-only hipcc build (no device code) of qft_emu.cpp, which includes the
+library's kernel bodies and schedules unchanged.  -O0 keeps the template-heavy
+build to seconds; the emulated problems are small.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+SRC = os.path.join(HERE, "qft_emu.cpp")
+LIB = os.path.join(HERE, "libqft_emu.so")
+DEPS = [SRC] + [os.path.join(ROOT, "paper_1301_0763_amd", "csrc", f)
+                for f in ("qft_device.hpp", "qft_schedule.hpp")]
+
+
+def build(force=True):
+    if not force and os.path.exists(LIB) and \
+            all(os.path.getmtime(d) <= os.path.getmtime(LIB) for d in DEPS):
+        return LIB
+    hipcc = "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc"
+    cmd = [hipcc, "-x", "hip", "--offload-host-only", "-O0", "-std=c++20", "-fPIC", "-shared",
+           SRC, "-o", LIB + ".tmp", "-lpthread"]
+    subprocess.run(cmd, check=True, capture_output=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+def load():
+    import ctypes
+    L = ctypes.CDLL(build(force=False))
+    i, vp, i64 = ctypes.c_int, ctypes.c_void_p, ctypes.c_int64
+    L.emu_tile.argtypes = [i, i, vp, vp, i, i, i]
+    L.emu_multipass.argtypes = [i, i, vp, vp, i, i64, i, i]
+    L.emu_uneven.argtypes = [i, i, vp, vp, ctypes.POINTER(ctypes.c_int32), i64, i, i, i]
+    for f in (L.emu_tile, L.emu_multipass, L.emu_uneven):
+        f.restype = i
+    return L
+
+
+if __name__ == "__main__":
+    print(build())

@@ -1,0 +1,292 @@
+// CPU emulation of the improved-QFT GPU library, for tests.
+//
+// Runs the unchanged kernel bodies of paper_1301_0763_amd/csrc/qft_device.hpp
+// and the host schedules of qft_schedule.hpp on the CPU:
+//  * a workgroup is emulated by `nthr` OS threads and a std::barrier;
+//  * every LDS (and heap-buffer) access goes through a tracking pointer; at
+//    each barrier (and at the end of every emulated global pass) a cell that
+//    was written by one thread and touched by another within the same phase
+//    is counted as a race.
+// Entry points return the number of races found (>= 0) or a negative error.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <barrier>
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../paper_1301_0763_amd/csrc/qft_device.hpp"
+#include "../../paper_1301_0763_amd/csrc/qft_schedule.hpp"
+
+namespace {
+
+struct Entry {
+  int64_t cell;
+  int64_t actor;
+  bool write;
+};
+
+struct Tracker {
+  std::vector<std::vector<Entry>> logs;  // one per OS thread slot
+  int64_t races = 0;
+  std::atomic<int64_t> oob{0};  // accesses outside the tracked buffer
+  explicit Tracker(int slots) : logs(slots) {}
+  void end_phase() {
+    struct St {
+      int64_t actor;
+      bool multi;
+      bool written;
+    };
+    std::unordered_map<int64_t, St> m;
+    for (auto& lg : logs) {
+      for (const Entry& e : lg) {
+        auto it = m.find(e.cell);
+        if (it == m.end()) {
+          m.emplace(e.cell, St{e.actor, false, e.write});
+        } else {
+          if (it->second.actor != e.actor) it->second.multi = true;
+          it->second.written |= e.write;
+        }
+      }
+      lg.clear();
+    }
+    for (auto& kv : m)
+      if (kv.second.multi && kv.second.written) ++races;
+  }
+};
+
+thread_local int tl_slot = 0;       // which log this OS thread appends to
+thread_local int64_t tl_actor = 0;  // emulated GPU thread / work item
+
+struct Ref {
+  float2* p;
+  int64_t cell;
+  Tracker* tr;
+  operator float2() const {
+    tr->logs[tl_slot].push_back({cell, tl_actor, false});
+    return *p;
+  }
+  Ref& operator=(float2 v) {
+    tr->logs[tl_slot].push_back({cell, tl_actor, true});
+    *p = v;
+    return *this;
+  }
+  Ref& operator=(const Ref& r) { return *this = (float2)r; }
+};
+
+struct TPtr {
+  float2* base;
+  int64_t off;
+  Tracker* tr;
+  int64_t size;  // cells of the buffer starting at base
+  Ref operator[](int64_t i) const {
+    static float2 sink;
+    if (off + i < 0 || off + i >= size) {
+      tr->oob++;
+      return Ref{&sink, -1, tr};
+    }
+    return Ref{base + off + i, (int64_t)(uintptr_t)(base + off + i), tr};
+  }
+  Ref operator*() const { return (*this)[0]; }
+  TPtr operator+(int64_t d) const { return TPtr{base, off + d, tr, size}; }
+};
+
+// Runs fn(tid, sync) on nthr threads sharing one barrier whose completion
+// closes a tracker phase.
+template <class F>
+void run_workgroup(int nthr, Tracker& tr, F fn) {
+  auto done = [&tr]() noexcept { tr.end_phase(); };
+  std::barrier bar(nthr, done);
+  struct HostSync {
+    decltype(bar)* b;
+    void operator()() const { b->arrive_and_wait(); }
+  };
+  std::vector<std::thread> th;
+  for (int t = 0; t < nthr; ++t) {
+    th.emplace_back([&, t]() {
+      tl_slot = t;
+      tl_actor = t;
+      fn(t, HostSync{&bar});
+    });
+  }
+  for (auto& x : th) x.join();
+  tr.end_phase();
+}
+
+constexpr int kEmuMaxi = 128;
+
+template <int DT, bool SWAP>
+int tile_impl(const void* x, void* X, int logn, int T, const int64_t* offs, const float* sec,
+              int nthr) {
+  using E = typename qftk::Store<DT>::T;
+  const int64_t cells = (int64_t)T << logn;
+  if ((cells / 2 + nthr - 1) / nthr > kEmuMaxi) return -2;
+  std::vector<float2> lds(cells);
+  Tracker tr(nthr);
+  TPtr W{lds.data(), 0, &tr, cells};
+  run_workgroup(nthr, tr, [&](int tid, auto sync) {
+    qftk::tile_body<DT, SWAP, kEmuMaxi>((const E*)x, (E*)X, W, logn, T, offs, sec, tid, nthr,
+                                        sync);
+  });
+  return tr.oob ? -100 : (int)tr.races;
+}
+
+std::vector<float> secants(int lg) {
+  lg = lg < 3 ? 3 : lg;
+  std::vector<float> s(((size_t)1 << lg) / 4);
+  qftk::fill_secants(s.data(), lg);  // the library's host generator
+  return s;
+}
+
+template <int DT, bool SWAP>
+struct EmuMultipass {
+  using E = typename qftk::Store<DT>::T;
+  const E* x;
+  E* X;
+  int logn;
+  int64_t batch;
+  int seg_log2;
+  int nthr;
+  const float* sec;
+  float2* cur;
+  float2* oth;
+  int64_t cells;
+  Tracker gtr{1};
+  int64_t races = 0;
+  template <class F>
+  void items(int64_t total, F f) {
+    tl_slot = 0;
+    for (int64_t i = 0; i < total; ++i) {
+      tl_actor = i;
+      f(i);
+    }
+    gtr.end_phase();
+  }
+  TPtr G(float2* p) { return TPtr{p, 0, &gtr, cells}; }
+  void fold() {
+    items(batch << (logn - 1), [&](int64_t i) { qftk::mp_fold_item<DT, SWAP>(x, G(cur), logn, i); });
+  }
+  void fwd(int K, int hi) {
+    const int64_t total = (2 * batch) << (logn - K - 2);
+    if (K == 3) items(total, [&](int64_t i) { qftk::mp_fwd_item<3>(G(cur), logn, hi, sec, i); });
+    else if (K == 2) items(total, [&](int64_t i) { qftk::mp_fwd_item<2>(G(cur), logn, hi, sec, i); });
+    else items(total, [&](int64_t i) { qftk::mp_fwd_item<1>(G(cur), logn, hi, sec, i); });
+  }
+  template <int MC_LOG2>
+  void segment_mc() {
+    const int per_t = qftk::mp_segment_blocks(logn, MC_LOG2);
+    for (int64_t b = 0; b < batch * per_t; ++b) {
+      const int64_t t = b / per_t;
+      const int r = (int)(b - t * per_t);
+      std::vector<float2> lds((size_t)2 << MC_LOG2);
+      Tracker ltr(nthr);
+      TPtr L{lds.data(), 0, &ltr, (int64_t)2 << MC_LOG2};
+      float2* wt = cur + (t << logn);
+      run_workgroup(nthr, ltr, [&](int tid, auto sync) {
+        qftk::mp_segment_body<MC_LOG2, kEmuMaxi>(wt, L, logn, r, sec, tid, nthr, sync);
+      });
+      races += ltr.races;
+      if (ltr.oob) races = -1000000;
+    }
+  }
+  void segment() {
+    switch (seg_log2) {
+      case 3: segment_mc<3>(); break;
+      case 4: segment_mc<4>(); break;
+      case 5: segment_mc<5>(); break;
+      case 6: segment_mc<6>(); break;
+      case 8: segment_mc<8>(); break;
+      case 10: segment_mc<10>(); break;
+      case 12: segment_mc<12>(); break;
+      default: races = -1000000; break;
+    }
+  }
+  void bwd(int s) {
+    items((2 * batch) << (logn - 2),
+          [&](int64_t i) { qftk::mp_bwd_item(G(cur), G(oth), logn, s, i); });
+    std::swap(cur, oth);
+  }
+  void chain(int p) {
+    items(batch * qftk::chain_groups(p), [&](int64_t i) { qftk::mp_chain_item(G(cur), logn, p, i); });
+  }
+  void combine() {
+    items(batch << (logn - 1), [&](int64_t i) { qftk::mp_combine_item<DT, SWAP>(G(cur), X, logn, i); });
+  }
+};
+
+template <int DT, bool SWAP>
+int multipass_impl(const void* x, void* X, int logn, int64_t batch, int seg_log2, int nthr,
+                   const float* sec) {
+  using E = typename qftk::Store<DT>::T;
+  if (logn < seg_log2 + 3) return -3;
+  std::vector<float2> w0((size_t)batch << logn), w1((size_t)batch << logn);
+  EmuMultipass<DT, SWAP> ex{(const E*)x, (E*)X, logn, batch, seg_log2, nthr, sec,
+                            w0.data(), w1.data(), (int64_t)batch << logn};
+  qftk::multipass_schedule(ex, logn, seg_log2);
+  if (ex.races < 0 || ex.gtr.oob) return -4;
+  return (int)(ex.races + ex.gtr.races);
+}
+
+template <int DT, bool SWAP>
+int uneven_impl(const void* x, void* X, const int32_t* log2n, int64_t count, int tile_log2,
+                int seg_log2, int nthr) {
+  using E = typename qftk::Store<DT>::T;
+  int mx = 3;
+  for (int64_t i = 0; i < count; ++i) mx = mx > log2n[i] ? mx : log2n[i];
+  std::vector<float> sec = secants(mx);
+  std::vector<int64_t> off, perm, large;
+  std::vector<qftk::TileDesc> tiles;
+  qftk::build_uneven_worklist(log2n, count, tile_log2, off, tiles, perm, large);
+  int races = 0;
+  for (const auto& d : tiles) {
+    int r = tile_impl<DT, SWAP>(x, X, d.log2n, d.count, perm.data() + d.first, sec.data(), nthr);
+    if (r < 0) return r;
+    races += r;
+  }
+  for (int64_t i : large) {
+    int r = multipass_impl<DT, SWAP>((const E*)x + off[i], (E*)X + off[i], log2n[i], 1, seg_log2,
+                                     nthr, sec.data());
+    if (r < 0) return r;
+    races += r;
+  }
+  return races;
+}
+
+}  // namespace
+
+extern "C" {
+
+int emu_tile(int dt, int swap, const void* x, void* X, int logn, int T, int nthr) {
+  if (logn < 1 || logn > 14 || T < 1 || nthr < 1) return -1;
+  std::vector<float> sec = secants(logn);
+  if (dt == 0) return swap ? tile_impl<0, true>(x, X, logn, T, nullptr, sec.data(), nthr)
+                           : tile_impl<0, false>(x, X, logn, T, nullptr, sec.data(), nthr);
+  return swap ? tile_impl<1, true>(x, X, logn, T, nullptr, sec.data(), nthr)
+              : tile_impl<1, false>(x, X, logn, T, nullptr, sec.data(), nthr);
+}
+
+int emu_multipass(int dt, int swap, const void* x, void* X, int logn, int64_t batch,
+                  int seg_log2, int nthr) {
+  if (logn < 4 || logn > 24 || batch < 1 || nthr < 1) return -1;
+  std::vector<float> sec = secants(logn);
+  if (dt == 0)
+    return swap ? multipass_impl<0, true>(x, X, logn, batch, seg_log2, nthr, sec.data())
+                : multipass_impl<0, false>(x, X, logn, batch, seg_log2, nthr, sec.data());
+  return swap ? multipass_impl<1, true>(x, X, logn, batch, seg_log2, nthr, sec.data())
+              : multipass_impl<1, false>(x, X, logn, batch, seg_log2, nthr, sec.data());
+}
+
+int emu_uneven(int dt, int swap, const void* x, void* X, const int32_t* log2n, int64_t count,
+               int tile_log2, int seg_log2, int nthr) {
+  if (count < 1 || nthr < 1) return -1;
+  if (dt == 0) return swap ? uneven_impl<0, true>(x, X, log2n, count, tile_log2, seg_log2, nthr)
+                           : uneven_impl<0, false>(x, X, log2n, count, tile_log2, seg_log2, nthr);
+  return swap ? uneven_impl<1, true>(x, X, log2n, count, tile_log2, seg_log2, nthr)
+              : uneven_impl<1, false>(x, X, log2n, count, tile_log2, seg_log2, nthr);
+}
+
+}  // extern "C"

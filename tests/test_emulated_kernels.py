@@ -1,0 +1,156 @@
+"""The GPU kernels' source, run on the CPU, against the FP64 oracle.
+
+tests/emu/qft_emu.cpp compiles the unchanged kernel bodies
+(paper_1301_0763_amd/csrc/qft_device.hpp) and host schedules
+(qft_schedule.hpp) for the host and runs each workgroup as OS threads with a
+barrier.  Every LDS and heap-buffer access is tracked: a cell written by one
+thread and touched by another between two barriers is a race.  These tests
+need no GPU; they check indexing, barriers and the multi-pass/uneven
+schedules (with small segment sizes, so that many passes occur at small N).
+
+Tolerance: FP32 arithmetic, relative RMS error (eq. qft_44 per signal)
+<= 1e-5 * log2 N against the FP64 oracle run on the FP32-rounded input.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import build as OB
+from oracle import direct as D
+from oracle import qft as Q
+from tests.emu import build as EB
+
+
+@pytest.fixture(scope="module")
+def emu():
+    return EB.load()
+
+
+def _as_c64(x):
+    return np.ascontiguousarray(x.astype(np.complex64))
+
+
+def _tol(logn):
+    return 1e-5 * logn
+
+
+def _ref(x64, swap=False):
+    x = x64.astype(np.complex128)
+    if x.shape[-1] >= 4096:
+        X = OB.cdft(np.conj(x) if swap else x)
+        return np.conj(X) if swap else X
+    return Q.qft_adjoint(x) if swap else Q.qft(x)
+
+
+def run_tile(emu, x, nthr=64, swap=0):
+    xf = _as_c64(x)
+    out = np.zeros_like(xf)
+    T, N = xf.shape
+    races = emu.emu_tile(0, swap, xf.ctypes.data, out.ctypes.data, N.bit_length() - 1, T, nthr)
+    assert races >= 0, races
+    return races, out
+
+
+@pytest.mark.parametrize("logn", range(1, 13))
+def test_tile_all_sizes(emu, logn):
+    N = 1 << logn
+    T = max(1, min(4, 4096 // N))
+    x = workloads.uniform(100 + logn, (T, N))
+    races, out = run_tile(emu, x)
+    assert races == 0
+    err = D.relative_l2(out, _ref(x))
+    assert err.max() <= _tol(logn), err.max()
+
+
+@pytest.mark.parametrize("logn,T,nthr", [(10, 4, 256), (12, 1, 256), (13, 1, 512), (8, 3, 64),
+                                          (5, 7, 32)])
+def test_tile_block_shapes_and_ragged(emu, logn, T, nthr):
+    """Real block sizes of the tile kernel, and a ragged last tile (T below
+    the tile capacity)."""
+    x = workloads.normal(7, (T, 1 << logn))
+    races, out = run_tile(emu, x, nthr=nthr)
+    assert races == 0
+    assert D.relative_l2(out, _ref(x)).max() <= _tol(logn)
+
+
+@pytest.mark.parametrize("logn", [1, 2, 3, 7, 11])
+def test_tile_adjoint(emu, logn):
+    x = workloads.uniform(9, (2, 1 << logn))
+    races, out = run_tile(emu, x, swap=1)
+    assert races == 0
+    assert D.relative_l2(out, _ref(x, swap=True)).max() <= _tol(logn)
+
+
+def test_tile_fp16_storage(emu):
+    logn, T = 9, 8
+    x = workloads.uniform(12, (T, 1 << logn))
+    x16 = np.stack([x.real, x.imag], -1).astype(np.float16)
+    out = np.zeros_like(x16)
+    races = emu.emu_tile(1, 0, x16.ctypes.data, out.ctypes.data, logn, T, 64)
+    assert races == 0
+    xin = x16[..., 0].astype(np.float64) + 1j * x16[..., 1].astype(np.float64)
+    got = out[..., 0].astype(np.float64) + 1j * out[..., 1].astype(np.float64)
+    # output rounding to FP16 dominates: ~2^-11 relative
+    assert D.relative_l2(got, Q.qft(xin)).max() < 1e-3
+
+
+def run_mp(emu, x, seg, nthr=16, swap=0):
+    xf = _as_c64(x)
+    out = np.zeros_like(xf)
+    B, N = xf.shape
+    races = emu.emu_multipass(0, swap, xf.ctypes.data, out.ctypes.data, N.bit_length() - 1, B,
+                              seg, nthr)
+    assert races >= 0, races
+    return races, out
+
+
+@pytest.mark.parametrize("seg,logn", [(3, 6), (3, 9), (4, 7), (4, 11), (5, 8), (5, 12),
+                                      (3, 12)])
+def test_multipass_small_segments(emu, seg, logn):
+    """The multi-pass schedule with segments of 2^seg cells (the library uses
+    2^12), so that the global forward/backward rounds and chain levels occur
+    at small N."""
+    x = workloads.normal(seg * 100 + logn, (2, 1 << logn))
+    races, out = run_mp(emu, x, seg)
+    assert races == 0
+    assert D.relative_l2(out, _ref(x)).max() <= _tol(logn)
+
+
+def test_multipass_adjoint(emu):
+    x = workloads.uniform(5, (2, 1 << 10))
+    races, out = run_mp(emu, x, 4, swap=1)
+    assert races == 0
+    assert D.relative_l2(out, _ref(x, swap=True)).max() <= _tol(10)
+
+
+@pytest.mark.slow
+def test_multipass_library_segment_size(emu):
+    """N = 2^15 with the library's own 2^12-cell segments."""
+    x = workloads.normal(15, (1, 1 << 15))
+    races, out = run_mp(emu, x, 12, nthr=64)
+    assert races == 0
+    assert D.relative_l2(out, _ref(x)).max() <= _tol(15)
+
+
+def test_uneven_worklist(emu):
+    """Packed uneven batch: small tiles (2^7 cells) so that several sizes share
+    the work list, and two transforms beyond the tile size go multi-pass
+    (segments of 2^3)."""
+    rng = np.random.default_rng(3)
+    log2n = np.array(list(rng.integers(1, 8, 40)) + [9, 10], dtype=np.int32)
+    rng.shuffle(log2n)
+    total = int(np.sum(1 << log2n.astype(np.int64)))
+    vals = workloads.uniform(21, (total,))
+    xf = _as_c64(vals)
+    out = np.zeros_like(xf)
+    races = emu.emu_uneven(0, 0, xf.ctypes.data, out.ctypes.data,
+                           log2n.ctypes.data_as(__import__("ctypes").POINTER(
+                               __import__("ctypes").c_int32)), log2n.size, 7, 3, 16)
+    assert races == 0
+    off = 0
+    for r in log2n:
+        N = 1 << int(r)
+        seg = xf[off:off + N][None]
+        err = D.relative_l2(out[off:off + N][None], _ref(seg)).max()
+        assert err <= _tol(max(int(r), 1)), (r, err)
+        off += N

@@ -1,0 +1,249 @@
+"""GPU parity: the gfx950 library (through the C ABI) against the FP64 oracle.
+
+Tolerance (FP32 arithmetic): relative RMS error per signal (eq. qft_44 before
+averaging), ||X - X_ref||_2 / ||X_ref||_2 <= 1e-5 * log2 N, with X_ref the
+FP64 oracle evaluated on the FP32 input.  FP16 storage is bound by the output
+rounding (2^-11 relative per element) and is held to 1e-3.
+"""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import build as OB
+from oracle import direct as D
+from oracle import qft as Q
+
+torch = pytest.importorskip("torch")
+import paper_1301_0763_amd as qft  # noqa: E402
+from paper_1301_0763_amd import _lib  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def tol(logn):
+    return 1e-5 * logn
+
+
+def ref_fwd(x):
+    x = np.asarray(x, dtype=np.complex128)
+    if x.shape[-1] <= 256:
+        return Q.qft(x)
+    return OB.cdft(x)
+
+
+def gpu_fwd(x, adjoint=False):
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+    y = qft.fft_adjoint(xt) if adjoint else qft.fft(xt)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def test_c1_against_direct_dft():
+    say("c1: N=1024 B=64 U[-1,1] seed 0, fwd vs O(N^2) DFT")
+    x = workloads.make("c1")
+    X = gpu_fwd(x)
+    err = D.relative_l2(X, D.dft(x.astype(np.complex128)))
+    say(f"c1 rel-L2 mean {err.mean():.3e} max {err.max():.3e}")
+    assert err.max() <= tol(10)
+
+
+@pytest.mark.parametrize("logn", range(1, 15))
+def test_all_tile_sizes(logn):
+    B = 3 if logn > 10 else 5
+    say(f"tile sizes: N=2^{logn} B={B}")
+    x = workloads.uniform(1000 + logn, (B, 1 << logn))
+    err = D.relative_l2(gpu_fwd(x), ref_fwd(x))
+    assert err.max() <= tol(logn), err.max()
+
+
+@pytest.mark.parametrize("logn,B", [(15, 3), (16, 2), (17, 1), (18, 1)])
+def test_multipass_sizes(logn, B):
+    say(f"multi-pass: N=2^{logn} B={B}")
+    x = workloads.normal(2000 + logn, (B, 1 << logn))
+    err = D.relative_l2(gpu_fwd(x), ref_fwd(x))
+    assert err.max() <= tol(logn), err.max()
+
+
+@pytest.mark.parametrize("logn,B", [(3, 4), (10, 6), (14, 2), (16, 2)])
+def test_adjoint_and_round_trip(logn, B):
+    say(f"adjoint: N=2^{logn} B={B}")
+    x = workloads.uniform(3000 + logn, (B, 1 << logn))
+    N = 1 << logn
+    y = gpu_fwd(x, adjoint=True)
+    ref = np.conj(ref_fwd(np.conj(x.astype(np.complex128))))
+    assert D.relative_l2(y, ref).max() <= tol(logn)
+    # bwd(fwd(x)) = N x
+    xt = torch.from_numpy(x).to(DEV)
+    rt = qft.fft_adjoint(qft.fft(xt)).cpu().numpy() / N
+    assert D.relative_l2(rt, x.astype(np.complex128)).max() <= 2 * tol(logn)
+    # dot-product test <F x, y> = <x, F^H y>
+    z = workloads.uniform(3100 + logn, (B, N))
+    Fx = gpu_fwd(x)
+    FHz = gpu_fwd(z, adjoint=True)
+    lhs = np.vdot(z.astype(np.complex128), Fx)
+    rhs = np.vdot(FHz, x.astype(np.complex128))
+    assert abs(lhs - rhs) <= tol(logn) * abs(lhs) * 10
+
+
+def test_c2_full_size():
+    say("c2: N=2^16 B=256 N(0,1) seed 1 (the benchmark workload), full compare")
+    x = workloads.make("c2")
+    X = gpu_fwd(x)
+    ref = OB.cdft(x.astype(np.complex128))
+    err = D.relative_l2(X, ref)
+    say(f"c2 rel-L2 mean {err.mean():.3e} max {err.max():.3e}")
+    assert err.max() <= tol(16)
+    # independent spot check against the DFT definition on sampled bins
+    bins = np.array([0, 1, 7, 4096, 32767, 32768, 32769, 65535])
+    direct_vals = D.dft_bins(x[:2].astype(np.complex128), bins)
+    scale = np.sqrt(np.mean(np.abs(ref[:2]) ** 2, axis=-1, keepdims=True))
+    assert np.max(np.abs(X[:2, bins] - direct_vals) / scale) < 1e-5 * 16
+
+
+def test_c3_single_large():
+    say("c3: N=2^24 B=1 tones+noise seed 2")
+    x, freqs, amps = workloads.make("c3")
+    X = gpu_fwd(x)
+    ref = OB.cdft(x.astype(np.complex128))
+    err = D.relative_l2(X, ref).max()
+    say(f"c3 rel-L2 {err:.3e} (target {tol(24):.1e})")
+    assert err <= tol(24)
+    N = 1 << 24
+    # closed form: |X(f_i)| ~ N a_i, far above the noise floor
+    got = np.abs(X[0, freqs])
+    np.testing.assert_allclose(got, N * amps, rtol=1e-3)
+
+
+def _uneven(dtype):
+    r, vals = workloads.make("c4")
+    if dtype == "c16":
+        v16 = vals.astype(np.complex64)
+        host = np.stack([v16.real, v16.imag], -1).astype(np.float16)
+        xin = host[..., 0].astype(np.float64) + 1j * host[..., 1].astype(np.float64)
+        t = torch.from_numpy(host).to(DEV).view(torch.complex32).reshape(-1)
+    else:
+        xin = vals.astype(np.complex128)
+        t = torch.from_numpy(vals).to(DEV)
+    out = qft.fft_packed(t, r.tolist())
+    torch.cuda.synchronize()
+    if dtype == "c16":
+        o = out.view(torch.float16).reshape(-1, 2).float().cpu().numpy().astype(np.float64)
+        got = o[:, 0] + 1j * o[:, 1]
+    else:
+        got = out.cpu().numpy().astype(np.complex128)
+    off = np.concatenate([[0], np.cumsum(1 << r.astype(np.int64))])
+    worst = 0.0
+    for lg in range(6, 15):
+        idx = np.nonzero(r == lg)[0]
+        N = 1 << lg
+        xs = np.stack([xin[off[i]:off[i] + N] for i in idx])
+        gs = np.stack([got[off[i]:off[i] + N] for i in idx])
+        e = D.relative_l2(gs, OB.cdft(xs)).max()
+        worst = max(worst, e / (tol(lg) if dtype == "c32" else 1e-3))
+    return worst
+
+
+def test_c4_uneven_fp32():
+    say("c4: 4096 uneven transforms r in 6..14, seed 3, FP32")
+    assert _uneven("c32") <= 1.0
+
+
+def test_c4_uneven_fp16_storage():
+    say("c4: uneven, FP16 storage")
+    assert _uneven("c16") <= 1.0
+
+
+def test_c5_autograd_loss_gradient():
+    say("c5: N=4096 B=512 loss = sum w |X|^2, autograd")
+    x, w = workloads.make("c5")
+    xt = torch.from_numpy(x).to(DEV).requires_grad_(True)
+    wt = torch.from_numpy(w).to(DEV)
+    X = qft.QFTFunction.apply(xt)
+    loss = (wt * X.abs() ** 2).sum()
+    loss.backward()
+    g = xt.grad.cpu().numpy().astype(np.complex128)
+    # analytic: for L = sum w |F x|^2, PyTorch's grad is 2 F^H (w * F x)
+    x64 = x.astype(np.complex128)
+    Xr = OB.cdft(x64)
+    gref = 2 * np.conj(OB.cdft(np.conj(w * Xr)))
+    err = D.relative_l2(g, gref).max()
+    say(f"c5 grad rel-L2 {err:.3e}")
+    assert err <= 2 * tol(12)
+
+
+def test_gradcheck_small_against_finite_differences():
+    """N = 64, B = 8, seed 4: the GPU vector-Jacobian product against FP64
+    central finite differences of the oracle (a linear map, so the FD are
+    exact up to rounding); tolerance from the FP32 bound."""
+    say("gradcheck N=64 B=8")
+    rng = np.random.default_rng(4)
+    N, B = 64, 8
+    x = (rng.uniform(-1, 1, (B, N)) + 1j * rng.uniform(-1, 1, (B, N))).astype(np.complex64)
+    v = (rng.uniform(-1, 1, (B, N)) + 1j * rng.uniform(-1, 1, (B, N))).astype(np.complex64)
+    xt = torch.from_numpy(x).to(DEV).requires_grad_(True)
+    X = qft.QFTFunction.apply(xt)
+    # scalar L = Re <v, X>; grad wrt x (PyTorch convention) = F^H v
+    L = (torch.from_numpy(v).to(DEV).conj() * X).real.sum()
+    L.backward()
+    g = xt.grad.cpu().numpy().astype(np.complex128)
+    x64 = x.astype(np.complex128)
+    h = 1e-3
+    fd = np.zeros_like(x64)
+    vv = v.astype(np.complex128)
+
+    def Lf(z):
+        return np.sum(np.real(np.conj(vv) * Q.qft(z)))
+
+    for b in range(B):
+        for n in range(N):
+            for part, unit in ((0, 1.0), (1, 1j)):
+                zp = x64.copy(); zp[b, n] += h * unit
+                zm = x64.copy(); zm[b, n] -= h * unit
+                d = (Lf(zp) - Lf(zm)) / (2 * h)
+                fd[b, n] += d if part == 0 else 1j * d
+    assert D.relative_l2(g, fd).max() <= 2 * tol(6)
+
+
+def test_in_place_and_errors():
+    say("in-place exec, alignment and overlap errors")
+    x = workloads.uniform(55, (4, 512))
+    t = torch.from_numpy(x).to(DEV)
+    p = qft.Plan(9, 4)
+    ref = p.forward(t).cpu().numpy()
+    qft.qft_exec_fwd(p.handle, t.data_ptr(), t.data_ptr(), 0)  # in place
+    torch.cuda.synchronize()
+    assert np.array_equal(t.cpu().numpy(), ref)
+    L = _lib.lib()
+    buf = torch.zeros(2 * 4 * 512 + 8, dtype=torch.complex64, device=DEV)
+    base = buf.data_ptr()
+    assert L.qft_exec_fwd(p.handle, base + 4, base + 4 * 512 * 8 * 2, None) == \
+        _lib.QFT_ERROR_ALIGNMENT
+    assert L.qft_exec_fwd(p.handle, base, base + 8 * 8, None) == _lib.QFT_ERROR_OVERLAP
+    p.close()
+    # multi-pass in place
+    x = workloads.uniform(56, (2, 1 << 15))
+    t = torch.from_numpy(x).to(DEV)
+    p = qft.Plan(15, 2)
+    ref = p.forward(t).cpu().numpy()
+    qft.qft_exec_fwd(p.handle, t.data_ptr(), t.data_ptr(), 0)
+    torch.cuda.synchronize()
+    assert np.array_equal(t.cpu().numpy(), ref)
+    p.close()
+
+
+def test_plan_info():
+    p = qft.Plan(16, 256)
+    info = p.info
+    assert info["total_points"] == 256 * 65536
+    assert info["algo_bytes"] == 2 * 256 * 65536 * 8
+    assert info["flops_actual"] == 256 * (4 * 65536 * 16 - 6 * 65536 + 8)
+    p.close()
