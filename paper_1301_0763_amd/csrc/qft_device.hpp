@@ -301,6 +301,167 @@ QFT_HD void chain_dst_group(SP ds, int P, int g) {
 }
 
 
+// ---------------------------------------------------------------------------
+// LDS pointer with padding: logical cell c is stored at base[c + (c >> PS)],
+// one spare cell per 2^PS cells, so that threads owning runs of cells at a
+// power-of-two stride do not collide on LDS banks.  PS >= 16 means no padding.
+// ---------------------------------------------------------------------------
+template <int PS>
+struct PadPtr {
+  float2* base;
+  int off;
+  QFT_HD float2& operator[](int i) const {
+    const int c = off + i;
+    return base[PS >= 16 ? c : c + (c >> (PS & 15))];
+  }
+  QFT_HD float2& operator*() const { return (*this)[0]; }
+  QFT_HD PadPtr operator+(int d) const { return PadPtr{base, off + d}; }
+};
+
+template <int PS>
+QFT_HD constexpr int padded_cells(int cells) {
+  return PS >= 16 ? cells : cells + (cells >> PS);
+}
+
+// ---------------------------------------------------------------------------
+// Fused innermost rounds: forward rounds S = 2^K .. 2 and then backward
+// rounds S = 2 .. 2^K on the whole segment j of 2^K cells, in registers.
+// ---------------------------------------------------------------------------
+template <int K, bool DST, typename SP>
+QFT_HD void tail_group(SP sd, int j, const float* __restrict__ sec, bool skip0) {
+  constexpr int S = 1 << K;
+  const int base = j * S;
+  float2 e[S];
+#pragma unroll
+  for (int c = 0; c < S; ++c) e[c] = sd[base + c];
+#pragma unroll
+  for (int m = K; m >= 1; --m) {
+    const int span = 1 << m, half = span >> 1;
+#pragma unroll
+    for (int c0 = 0; c0 < S; c0 += span) {
+      if (skip0 && j == 0 && c0 == 0) continue;
+#pragma unroll
+      for (int cc = 0; cc < half / 2 + (half & 1); ++cc) {
+        // butterflies cc and half-1-cc touch cells {cc, span-1-cc} and
+        // {half-1-cc, half+cc}; outputs go to {cc, half+cc, half-1-cc, span-1-cc}
+        const int c2 = half - 1 - cc;
+        const float2 a1 = e[c0 + cc], b1 = e[c0 + span - 1 - cc];
+        const float2 a2 = e[c0 + c2], b2 = e[c0 + span - 1 - c2];
+        const float h1 = sec[half + cc], h2 = sec[half + c2];
+        const float2 s1 = cadd(a1, b1), d1 = csub(a1, b1);
+        const float2 s2 = cadd(a2, b2), d2 = csub(a2, b2);
+        e[c0 + cc] = DST ? d1 : s1;
+        e[c0 + half + cc] = cscale(DST ? s1 : d1, h1);
+        if (c2 != cc) {
+          e[c0 + c2] = DST ? d2 : s2;
+          e[c0 + half + c2] = cscale(DST ? s2 : d2, h2);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 1; m <= K; ++m) {
+    const int span = 1 << m, half = span >> 1;
+#pragma unroll
+    for (int c0 = 0; c0 < S; c0 += span) {
+      if (skip0 && j == 0 && c0 == 0) continue;
+      float2 y[S];
+#pragma unroll
+      for (int i = 0; i < half; ++i) {
+        const float2 A = e[c0 + i], T = e[c0 + half + i];
+        if (!DST) {
+          y[2 * i] = A;
+          y[2 * i + 1] = (i + 1 < half) ? cadd(T, e[c0 + half + i + 1]) : T;
+        } else {
+          y[2 * i + 1] = A;
+          y[2 * i] = (i >= 1) ? cadd(e[c0 + half + i - 1], T) : T;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < span; ++i) e[c0 + i] = y[i];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < S; ++c) sd[base + c] = e[c];
+}
+
+// ---------------------------------------------------------------------------
+// K backward rounds S/2^(K-1) .. S on segment j (input: its 2^K sub-segments
+// of G = S/2^K cells, each a natural-order DCT-II/DST-II of length G).  The
+// thread with lane offset i < G computes the natural-order outputs
+// i*2^K .. i*2^K + 2^K - 1 of the segment.  Level by level, sub-segment pairs
+// (A, T) become Y(2e) = A(e), Y(2e+1) = T(e) + T(e+1) (DCT) or
+// Y(2e+1) = A(e), Y(2e) = T(e-1) + T(e) (DST); the one neighbour beyond the
+// thread's block is always an A-chain pass-through of an input cell at i+1
+// (DCT) or i-1 (DST), so it is loaded, not recomputed: 2^(K+1) - 1 loads,
+// K 2^(K-1) additions, no redundant arithmetic.
+// ---------------------------------------------------------------------------
+template <int K, bool DST, typename SP>
+QFT_HD void bwd_group_load(SP sd, int S, int j, int i, float2 (&y)[1 << K]) {
+  constexpr int R = 1 << K;
+  const int G = S >> K;
+  const int base = j * S;
+  float2 cur[R], halo[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) cur[c] = sd[base + c * G + i];
+  const bool has = DST ? (i >= 1) : (i + 1 < G);
+  const int hi = DST ? i - 1 : i + 1;
+#pragma unroll
+  for (int c = 0; c < R; ++c)
+    halo[c] = (c > 0 && has) ? (float2)sd[base + c * G + hi] : make_float2(0.f, 0.f);
+#pragma unroll
+  for (int m = 1; m <= K; ++m) {
+    const int len = 1 << m, hl = len >> 1;  // values per segment at level m / m-1
+    float2 nxt[R], nh[R];
+#pragma unroll
+    for (int c = 0; c < (R >> m); ++c) {
+      const int a0 = (2 * c) * hl, t0 = (2 * c + 1) * hl;  // A and T in cur
+#pragma unroll
+      for (int e = 0; e < hl; ++e) {
+        const float2 A = cur[a0 + e], T = cur[t0 + e];
+        if (!DST) {
+          nxt[c * len + 2 * e] = A;
+          nxt[c * len + 2 * e + 1] = cadd(T, (e + 1 < hl) ? cur[t0 + e + 1] : halo[2 * c + 1]);
+        } else {
+          nxt[c * len + 2 * e + 1] = A;
+          nxt[c * len + 2 * e] = cadd((e >= 1) ? cur[t0 + e - 1] : halo[2 * c + 1], T);
+        }
+      }
+      nh[c] = halo[2 * c];
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) cur[c] = nxt[c];
+#pragma unroll
+    for (int c = 0; c < (R >> m); ++c) halo[c] = nh[c];
+  }
+#pragma unroll
+  for (int c = 0; c < R; ++c) y[c] = cur[c];
+}
+
+// The segment j == 0 of a side head (heap) holds the blocks M = 2G, 4G, ..,
+// S/2 that still need a rounds each (M = G 2^a); the lane-i thread loads the
+// a-level groups of all of them into out[] (2^K - 2 values).
+template <int K, bool DST, int A, typename SP>
+QFT_HD void bwd_head_load(SP sd, int G, int i, float2* out) {
+  if constexpr (A < K) {
+    float2 y[1 << A];
+    bwd_group_load<A, DST>(sd, G << A, 1, i, y);
+#pragma unroll
+    for (int e = 0; e < (1 << A); ++e) out[e] = y[e];
+    bwd_head_load<K, DST, A + 1>(sd, G, i, out + (1 << A));
+  }
+}
+
+template <int K, int A, typename SP>
+QFT_HD void bwd_head_store(SP sd, int G, int i, const float2* in) {
+  if constexpr (A < K) {
+    const int M = G << A;
+#pragma unroll
+    for (int e = 0; e < (1 << A); ++e) sd[M + i * (1 << A) + e] = in[e];
+    bwd_head_store<K, A + 1>(sd, G, i, in + (1 << A));
+  }
+}
+
 // ===========================================================================
 // Sweeps over a workgroup's buffer.  A "side" is one half of a transform's
 // heap (DCT or DST); transforms alternate DCT/DST sides, an isolated segment
@@ -459,49 +620,240 @@ QFT_HD void mid_sweeps(WP W, int logn, int T, const float* sec, int tid, int nth
 }
 
 // ===========================================================================
+// Register-blocked sweeps.  CPT = cells per thread of the workgroup buffer
+// (buffer cells / threads, compile time) bounds the registers each thread
+// holds across the load/store barrier of a backward chunk.
+// ===========================================================================
+// Forward rounds S = 2^hi .. 2^(hi-K+1), G = 2^(hi-K) >= 2 (in place).
+template <int K, int CPT, typename WP>
+QFT_HD void fwd_chunk2(WP W, int lgside, int nsides, int mode, int hi, bool skip0,
+                       const float* sec, int tid, int nthr) {
+  constexpr int NI = (CPT + (2 << K) - 1) / (2 << K);  // groups per thread
+  const int lgGroups = lgside - K - 1;
+  const int total = nsides << lgGroups;
+  const int lgHalfG = hi - K - 1;
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int i = tid + it * nthr;
+    if (i < total) {
+      const int s = i >> lgGroups;
+      const int g = i & ((1 << lgGroups) - 1);
+      const int j = g >> lgHalfG;
+      const int x = g & ((1 << lgHalfG) - 1);
+      auto sd = W + (s << lgside);
+      if (side_is_dst(mode, s)) fwd_group<K, true>(sd, 1 << hi, j, x, sec, skip0);
+      else fwd_group<K, false>(sd, 1 << hi, j, x, sec, skip0);
+    }
+  }
+}
+
+// Fused innermost rounds on whole segments of 2^K cells (in place).
+template <int K, int CPT, typename WP>
+QFT_HD void tail_chunk(WP W, int lgside, int nsides, int mode, bool skip0, const float* sec,
+                       int tid, int nthr) {
+  constexpr int NI = (CPT + (1 << K) - 1) / (1 << K);  // segments per thread
+  const int lgGroups = lgside - K;
+  const int total = nsides << lgGroups;
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int i = tid + it * nthr;
+    if (i >= total) break;
+    const int s = i >> lgGroups;
+    const int g = i & ((1 << lgGroups) - 1);
+    auto sd = W + (s << lgside);
+    if (side_is_dst(mode, s)) tail_group<K, true>(sd, g, sec, skip0);
+    else tail_group<K, false>(sd, g, sec, skip0);
+  }
+}
+
+// K backward rounds S = 2^lo .. 2^(lo+K-1): load, barrier, store, barrier.
+template <int K, int CPT, class Sync, typename WP>
+QFT_HD void bwd_chunk2(WP W, int lgside, int nsides, int mode, int lo, bool skip0, int tid,
+                       int nthr, Sync sync) {
+  constexpr int R = 1 << K;
+  constexpr int MAXG = (CPT >> K) > 0 ? (CPT >> K) : 1;
+  const int S = 1 << (lo + K - 1);
+  const int lgG = lo - 1;
+  const int lgGroups = lgside - K;  // thread groups (j, i) per side
+  const int total = nsides << lgGroups;
+  float2 y[MAXG][R];
+#pragma unroll
+  for (int it = 0; it < MAXG; ++it) {
+    const int i = tid + it * nthr;
+    if (i < total) {
+      const int s = i >> lgGroups;
+      const int g = i & ((1 << lgGroups) - 1);
+      const int j = g >> lgG, ii = g & ((1 << lgG) - 1);
+      auto sd = W + (s << lgside);
+      const bool dst = side_is_dst(mode, s);
+      if (skip0 && j == 0) {
+        if (dst) bwd_head_load<K, true, 1>(sd, 1 << lgG, ii, y[it]);
+        else bwd_head_load<K, false, 1>(sd, 1 << lgG, ii, y[it]);
+      } else {
+        if (dst) bwd_group_load<K, true>(sd, S, j, ii, y[it]);
+        else bwd_group_load<K, false>(sd, S, j, ii, y[it]);
+      }
+    }
+  }
+  sync();
+#pragma unroll
+  for (int it = 0; it < MAXG; ++it) {
+    const int i = tid + it * nthr;
+    if (i < total) {
+      const int s = i >> lgGroups;
+      const int g = i & ((1 << lgGroups) - 1);
+      const int j = g >> lgG, ii = g & ((1 << lgG) - 1);
+      auto sd = W + (s << lgside);
+      if (skip0 && j == 0) {
+        bwd_head_store<K, 1>(sd, 1 << lgG, ii, y[it]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < R; ++e) sd[j * S + ii * R + e] = y[it][e];
+      }
+    }
+  }
+  sync();
+}
+
+// Forward rounds S = 2^top .. 2^1 and backward rounds back up, with the
+// innermost KT rounds fused in registers and the others in chunks of <= 3.
+template <int CPT, class Sync, typename WP>
+QFT_HD void sweeps2(WP W, int lgside, int nsides, int mode, int top, bool skip0,
+                    const float* sec, int tid, int nthr, Sync sync) {
+  constexpr int KT = 3, KC = 3;
+  if (top < 1) return;
+  const int kt = top < KT ? top : KT;
+  // forward chunks above the tail, from the top: rounds (kt, top]
+  for (int hi = top; hi > kt;) {
+    const int K = (hi - kt) < KC ? (hi - kt) : KC;
+    if (K == 3) fwd_chunk2<3, CPT>(W, lgside, nsides, mode, hi, skip0, sec, tid, nthr);
+    else if (K == 2) fwd_chunk2<2, CPT>(W, lgside, nsides, mode, hi, skip0, sec, tid, nthr);
+    else fwd_chunk2<1, CPT>(W, lgside, nsides, mode, hi, skip0, sec, tid, nthr);
+    sync();
+    hi -= K;
+  }
+  if (kt == 3) tail_chunk<3, CPT>(W, lgside, nsides, mode, skip0, sec, tid, nthr);
+  else if (kt == 2) tail_chunk<2, CPT>(W, lgside, nsides, mode, skip0, sec, tid, nthr);
+  else tail_chunk<1, CPT>(W, lgside, nsides, mode, skip0, sec, tid, nthr);
+  sync();
+  // backward chunks above the tail, from the bottom: rounds (kt, top]
+  for (int lo = kt + 1; lo <= top;) {
+    const int K = (top - lo + 1) < KC ? (top - lo + 1) : KC;
+    if (K == 3) bwd_chunk2<3, CPT>(W, lgside, nsides, mode, lo, skip0, tid, nthr, sync);
+    else if (K == 2) bwd_chunk2<2, CPT>(W, lgside, nsides, mode, lo, skip0, tid, nthr, sync);
+    else bwd_chunk2<1, CPT>(W, lgside, nsides, mode, lo, skip0, tid, nthr, sync);
+    lo += K;
+  }
+}
+
+// Chain levels P = 2 .. 2^logn for T transforms.  Levels up to 2^pw run
+// wave-synchronously (one wave per transform, `wsync` orders its LDS
+// accesses); the larger levels are one block-synchronised pass each.
+template <class Sync, class WSync, typename WP>
+QFT_HD void chain2(WP W, int logn, int T, int tid, int nthr, int wave_size, Sync sync,
+                   WSync wsync) {
+  constexpr int PW = 9;
+  const int pw = logn < PW ? logn : PW;
+  const int nwaves = (nthr + wave_size - 1) / wave_size;
+  const int wave = tid / wave_size, lane = tid - wave * wave_size;
+  const int wlanes = (nthr - wave * wave_size) < wave_size ? (nthr - wave * wave_size) : wave_size;
+  const int rounds = (T + nwaves - 1) / nwaves;
+  for (int r = 0; r < rounds; ++r) {
+    const int t = wave + r * nwaves;
+    for (int p = 1; p <= pw; ++p) {
+      if (t < T) {
+        const int per_t = chain_groups(p);
+        for (int g = lane; g < per_t; g += wlanes) chain_item(W + (t << logn), logn, p, g);
+      }
+      wsync();
+    }
+  }
+  sync();
+  for (int p = pw + 1; p <= logn; ++p) {
+    const int per_t = chain_groups(p);
+    const int total = T * per_t;
+    for (int i = tid; i < total; i += nthr) {
+      const int t = i / per_t;
+      const int g = i - t * per_t;
+      chain_item(W + (t << logn), logn, p, g);
+    }
+    sync();
+  }
+}
+
+// Everything between fold and combine for T transforms of 2^logn cells.
+template <int CPT, class Sync, class WSync, typename WP>
+QFT_HD void mid_sweeps2(WP W, int logn, int T, const float* sec, int tid, int nthr,
+                        int wave_size, Sync sync, WSync wsync) {
+  if (logn >= 3) sweeps2<CPT>(W, logn - 1, 2 * T, SIDES_ALT, logn - 2, true, sec, tid, nthr, sync);
+  chain2(W, logn, T, tid, nthr, wave_size, sync, wsync);
+}
+
+// ===========================================================================
 // Whole-transform work of one workgroup: T transforms of length 2^logn.
 // Transform t is read from x + off(t) and written to X + off(t), with
 // off(t) = offs[t] when offs is given, else t * 2^logn.
 // ===========================================================================
-template <int DT, bool SWAP, int MAXI, class Sync, typename WP>
+template <int DT, bool SWAP, int CPT, class Sync, class WSync, typename WP>
 QFT_HD void tile_body(const typename Store<DT>::T* x, typename Store<DT>::T* X, WP W, int logn,
                       int T, const int64_t* offs, const float* sec, int tid, int nthr,
-                      Sync sync) {
+                      int wave_size, Sync sync, WSync wsync) {
+  // every thread owns at most FI fold/combine items (cell pairs); all global
+  // loads of a thread are issued before the first use so they overlap
+  constexpr int FI = (CPT + 1) / 2;
   const int n = 1 << logn, h = n >> 1;
   const int total = T << (logn - 1);
-  for (int i = tid; i < total; i += nthr) {
-    const int t = i >> (logn - 1);
-    const int m = i & (h - 1);
-    const int64_t o = offs ? offs[t] : ((int64_t)t << logn);
-    const typename Store<DT>::T* xt = x + o;
-    auto w = W + (t << logn);
-    if (m == 0) {
-      w[0] = sw<SWAP>(Store<DT>::ld(xt, 0));
-      w[h] = sw<SWAP>(Store<DT>::ld(xt, h));
-    } else {
-      const float2 a = sw<SWAP>(Store<DT>::ld(xt, m));
-      const float2 b = sw<SWAP>(Store<DT>::ld(xt, n - m));
-      const int l = __builtin_ctz(m);
-      const int cell = (n >> (l + 2)) + (m >> (l + 1));
-      w[cell] = cadd(a, b);
-      w[h + cell] = csub(a, b);
+  float2 av[FI], bv[FI];
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    const int i = tid + it * nthr;
+    if (i < total) {
+      const int t = i >> (logn - 1);
+      const int m = i & (h - 1);
+      const int64_t o = offs ? offs[t] : ((int64_t)t << logn);
+      const typename Store<DT>::T* xt = x + o;
+      av[it] = Store<DT>::ld(xt, m);
+      bv[it] = Store<DT>::ld(xt, m == 0 ? h : n - m);
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    const int i = tid + it * nthr;
+    if (i < total) {
+      const int t = i >> (logn - 1);
+      const int m = i & (h - 1);
+      auto w = W + (t << logn);
+      const float2 a = sw<SWAP>(av[it]), b = sw<SWAP>(bv[it]);
+      if (m == 0) {
+        w[0] = a;  // c(0)
+        w[h] = b;  // c(N/2)
+      } else {
+        const int l = __builtin_ctz(m);
+        const int cell = (n >> (l + 2)) + (m >> (l + 1));
+        w[cell] = cadd(a, b);
+        w[h + cell] = csub(a, b);
+      }
     }
   }
   sync();
-  mid_sweeps<MAXI>(W, logn, T, sec, tid, nthr, sync);
-  for (int i = tid; i < total; i += nthr) {
-    const int t = i >> (logn - 1);
-    const int k = i & (h - 1);
-    const int64_t o = offs ? offs[t] : ((int64_t)t << logn);
-    typename Store<DT>::T* Xt = X + o;
-    auto w = W + (t << logn);
-    if (k == 0) {
-      Store<DT>::st(Xt, 0, sw<SWAP>(w[0]));
-      Store<DT>::st(Xt, h, sw<SWAP>(w[h]));
-    } else {
-      const float2 C = w[k], S = w[h + k];
-      Store<DT>::st(Xt, k, sw<SWAP>(make_float2(C.x + S.y, C.y - S.x)));
-      Store<DT>::st(Xt, n - k, sw<SWAP>(make_float2(C.x - S.y, C.y + S.x)));
+  mid_sweeps2<CPT>(W, logn, T, sec, tid, nthr, wave_size, sync, wsync);
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    const int i = tid + it * nthr;
+    if (i < total) {
+      const int t = i >> (logn - 1);
+      const int k = i & (h - 1);
+      const int64_t o = offs ? offs[t] : ((int64_t)t << logn);
+      typename Store<DT>::T* Xt = X + o;
+      auto w = W + (t << logn);
+      if (k == 0) {
+        Store<DT>::st(Xt, 0, sw<SWAP>(w[0]));
+        Store<DT>::st(Xt, h, sw<SWAP>(w[h]));
+      } else {
+        const float2 C = w[k], S = w[h + k];
+        Store<DT>::st(Xt, k, sw<SWAP>(make_float2(C.x + S.y, C.y - S.x)));
+        Store<DT>::st(Xt, n - k, sw<SWAP>(make_float2(C.x - S.y, C.y + S.x)));
+      }
     }
   }
 }
@@ -604,33 +956,57 @@ QFT_HD void mp_chain_item(WP W, int logn, int p, int64_t i) {
 // r == 0: the core (both side heads [0, MC), a virtual transform of 2 MC
 // cells; chain to P = 2 MC); r >= 1: segment j >= 1 of the DCT side, then of
 // the DST side (rounds S = MC .. 2 and back; every sub-segment is a block).
-template <int MC_LOG2, int MAXI, class Sync, typename GP, typename LP>
+template <int MC_LOG2, int CPT, class Sync, class WSync, typename GP, typename LP>
 QFT_HD void mp_segment_body(GP wt, LP L, int logn, int r, const float* sec, int tid, int nthr,
-                            Sync sync) {
+                            int wave_size, Sync sync, WSync wsync) {
   constexpr int MC = 1 << MC_LOG2;
   const int h = 1 << (logn - 1);
   const int segs = h >> MC_LOG2;
+  // CPT = cells per thread for the 2*MC-cell core; the copies below issue all
+  // of a thread's global loads before the LDS stores
   if (r == 0) {
-    for (int i = tid; i < 2 * MC; i += nthr) {
-      const int side = i >> MC_LOG2, c = i & (MC - 1);
-      L[i] = (float2)wt[side * h + c];
+    float2 v[CPT];
+#pragma unroll
+    for (int it = 0; it < CPT; ++it) {
+      const int i = tid + it * nthr;
+      if (i < 2 * MC) v[it] = wt[(i >> MC_LOG2) * h + (i & (MC - 1))];
+    }
+#pragma unroll
+    for (int it = 0; it < CPT; ++it) {
+      const int i = tid + it * nthr;
+      if (i < 2 * MC) L[i] = v[it];
     }
     sync();
-    mid_sweeps<MAXI>(L, MC_LOG2 + 1, 1, sec, tid, nthr, sync);
-    for (int i = tid; i < 2 * MC; i += nthr) {
-      const int side = i >> MC_LOG2, c = i & (MC - 1);
-      wt[side * h + c] = (float2)L[i];
+    mid_sweeps2<CPT>(L, MC_LOG2 + 1, 1, sec, tid, nthr, wave_size, sync, wsync);
+#pragma unroll
+    for (int it = 0; it < CPT; ++it) {
+      const int i = tid + it * nthr;
+      if (i < 2 * MC) wt[(i >> MC_LOG2) * h + (i & (MC - 1))] = (float2)L[i];
     }
   } else {
     const int side = (r - 1) / (segs - 1);
     const int j = 1 + (r - 1) - side * (segs - 1);
     auto seg = wt + (side * h + j * MC);
-    for (int i = tid; i < MC; i += nthr) L[i] = (float2)seg[i];
+    constexpr int NI = (CPT + 1) / 2;
+    float2 v[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int i = tid + it * nthr;
+      if (i < MC) v[it] = seg[i];
+    }
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int i = tid + it * nthr;
+      if (i < MC) L[i] = v[it];
+    }
     sync();
     const int mode = side ? SIDES_DST : SIDES_DCT;
-    forward_sweep(L, MC_LOG2, 1, mode, MC_LOG2, 1, false, sec, tid, nthr, sync);
-    backward_sweep<MAXI>(L, MC_LOG2, 1, mode, 1, MC_LOG2, false, tid, nthr, sync);
-    for (int i = tid; i < MC; i += nthr) seg[i] = (float2)L[i];
+    sweeps2<CPT>(L, MC_LOG2, 1, mode, MC_LOG2, false, sec, tid, nthr, sync);
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int i = tid + it * nthr;
+      if (i < MC) seg[i] = (float2)L[i];
+    }
   }
 }
 
@@ -639,5 +1015,207 @@ QFT_HD int mp_segment_blocks(int logn, int mc_log2) {
   const int segs = 1 << (logn - 1 - mc_log2);
   return 1 + 2 * (segs - 1);
 }
+
+
+// ===========================================================================
+// Two-pass path for N = 8 MC, MC = 2^MC_LOG2 (one LDS segment = MC cells).
+// A side has 4 MC cells: segment 0 is the head (blocks < MC, the DCT-0/DST-0
+// chain up to P = 2 MC), segment 1 is the block of size MC, segments 2 and 3
+// are the two halves of the block of size 2 MC (= N/4) after its top forward
+// round.  Pass A: one workgroup per (transform, side, segment) gathers its
+// cells straight from x (real fold of Sec. 4.2, and the top round for
+// segments 2/3), runs the segment's remaining rounds in LDS and writes the
+// heap buffer.  Pass B: streaming; the top backward round of block N/4, chain
+// levels P = N/2 and N (eqs. qft_5C/5D/6) and the cdft combine (Sec. 4.1).
+// ===========================================================================
+// One side's DCT-0 (or DST-0) chain, levels P = 2 (4 for DST) .. 2^plog, on
+// side cells sd[0 .. 2^(plog-1)) with the DCT top cell at *top.
+template <bool DST, class Sync, class WSync, typename SP>
+QFT_HD void chain_one_side(SP sd, SP top, int plog, int tid, int nthr, int wave_size, Sync sync,
+                           WSync wsync) {
+  constexpr int PW = 9;
+  const int pw = plog < PW ? plog : PW;
+  // small levels: wave 0 alone, ordered by wave-level syncs that every
+  // thread executes (so that a full-barrier emulation stays uniform)
+  const int lanes = nthr < wave_size ? nthr : wave_size;
+  for (int p = DST ? 3 : 1; p <= pw; ++p) {
+    if (tid < wave_size) {
+      const int P = 1 << p;
+      if (!DST && P == 2) {
+        if (tid == 0) {
+          const float2 a = sd[0], b = *top;
+          sd[0] = cadd(a, b);
+          *top = csub(a, b);
+        }
+      } else {
+        const int ng = DST ? (P >> 3) : (P == 4 ? 1 : 1 + (P >> 3));
+        for (int g = tid; g < ng; g += lanes) {
+          if (DST) chain_dst_group(sd, P, g);
+          else chain_dct_group(sd, top, P, g);
+        }
+      }
+    }
+    wsync();
+  }
+  sync();
+  for (int p = (pw + 1 > (DST ? 3 : 1)) ? pw + 1 : (DST ? 3 : 1); p <= plog; ++p) {
+    const int P = 1 << p;
+    const int ng = DST ? (P >> 3) : 1 + (P >> 3);
+    for (int g = tid; g < ng; g += nthr) {
+      if (DST) chain_dst_group(sd, P, g);
+      else chain_dct_group(sd, top, P, g);
+    }
+    sync();
+  }
+}
+
+// Value of heap cell p (p >= 1) of one side of an N-point transform straight
+// from x: the folded sample c(n) = x(n) + x(N-n) (DCT) or d(n) = x(n) - x(N-n)
+// (DST) with n = (N / 4M)(2v+1) for the block M = 2^floor(log2 p), v = p - M.
+template <int DT, bool SWAP, bool DST>
+QFT_HD float2 heap_fold_value(const typename Store<DT>::T* xt, int logn, int p) {
+  const int lgM = 31 - __builtin_clz(p);
+  const int v = p - (1 << lgM);
+  const int n = (2 * v + 1) << (logn - 2 - lgM);
+  const float2 a = sw<SWAP>(Store<DT>::ld(xt, n));
+  const float2 b = sw<SWAP>(Store<DT>::ld(xt, (1 << logn) - n));
+  return DST ? csub(a, b) : cadd(a, b);
+}
+
+// Pass A for one workgroup: w = side * 4 + segment.
+template <int DT, bool SWAP, int MC_LOG2, int CPT, class Sync, class WSync, typename GP,
+          typename LP>
+QFT_HD void tp_pass_a(const typename Store<DT>::T* xt, GP wt, LP L, int w, const float* sec,
+                      int tid, int nthr, int wave_size, Sync sync, WSync wsync) {
+  constexpr int MC = 1 << MC_LOG2;
+  constexpr int logn = MC_LOG2 + 3;
+  constexpr int N = 1 << logn, h = N >> 1;
+  constexpr int NI = (CPT + 0) > 0 ? CPT : 1;  // cells per thread (MC / nthr)
+  const int side = w >> 2, j = w & 3;
+  const bool dst = side != 0;
+  // ---- gather ----
+  float2 v[NI];
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int q = tid + it * nthr;
+    if (q >= MC) continue;
+    const int p = j * MC + q;
+    if (j < 2) {
+      if (p == 0) {
+        v[it] = make_float2(0.f, 0.f);
+        if (!dst) v[it] = sw<SWAP>(Store<DT>::ld(xt, 0));  // c(0)
+      } else {
+        v[it] = dst ? heap_fold_value<DT, SWAP, true>(xt, logn, p)
+                    : heap_fold_value<DT, SWAP, false>(xt, logn, p);
+      }
+    } else {
+      // block N/4 (cells [2MC, 4MC)), top round S = 2MC: pair (q, 2MC-1-q),
+      // odd n = 2q+1 and its mirror N/2 - n
+      const int n = 2 * q + 1;
+      const float2 a0 = sw<SWAP>(Store<DT>::ld(xt, n));
+      const float2 b0 = sw<SWAP>(Store<DT>::ld(xt, N - n));
+      const float2 a1 = sw<SWAP>(Store<DT>::ld(xt, h - n));
+      const float2 b1 = sw<SWAP>(Store<DT>::ld(xt, h + n));
+      const float2 y0 = dst ? csub(a0, b0) : cadd(a0, b0);  // fold at n
+      const float2 y1 = dst ? csub(a1, b1) : cadd(a1, b1);  // fold at N/2 - n
+      const float2 sum = cadd(y0, y1), dif = csub(y0, y1);
+      if (j == 2) v[it] = dst ? dif : sum;
+      else v[it] = cscale(dst ? sum : dif, sec[MC + q]);
+    }
+  }
+  float2 topv = make_float2(0.f, 0.f);
+  if (!dst && j == 0 && tid == 0) topv = sw<SWAP>(Store<DT>::ld(xt, h));  // c(N/2)
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int q = tid + it * nthr;
+    if (q < MC) L[q] = v[it];
+  }
+  if (!dst && j == 0 && tid == 0) L[MC] = topv;
+  sync();
+  // ---- remaining rounds (and the chain for the heads) ----
+  const int mode = dst ? SIDES_DST : SIDES_DCT;
+  if (j == 0) {
+    sweeps2<CPT>(L, MC_LOG2, 1, mode, MC_LOG2 - 1, true, sec, tid, nthr, sync);
+    if (dst) chain_one_side<true>(L, L + MC, MC_LOG2 + 1, tid, nthr, wave_size, sync, wsync);
+    else chain_one_side<false>(L, L + MC, MC_LOG2 + 1, tid, nthr, wave_size, sync, wsync);
+  } else {
+    sweeps2<CPT>(L, MC_LOG2, 1, mode, MC_LOG2, false, sec, tid, nthr, sync);
+  }
+  // ---- write the segment to the heap buffer ----
+  auto seg = wt + (side * h + j * MC);
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int q = tid + it * nthr;
+    if (q < MC && !(dst && j == 0 && q == 0)) seg[q] = (float2)L[q];
+  }
+  if (!dst && j == 0 && tid == 0) wt[h] = (float2)L[MC];  // D_{2MC}(MC): top cell
+}
+
+// Pass B, thread k of a transform (0 <= k < N/8).  Heap contents after pass A
+// (DCT side; the DST side is alike with its own index conventions):
+//   cells [0, MC) + top : D_{N/4} (chain output of the head)
+//   cells [MC, 2MC)     : O1, the DCT-II of length N/8 (natural order)
+//   cells [2MC, 3MC)    : A, cells [3MC, 4MC): T, the halves of the block N/4
+// O0(2i) = A(i), O0(2i+1) = T(i) + T(i+1) (T(MC) = 0) is the top backward
+// round of the block N/4; then chain levels N/2 and N and the combine.
+template <int DT, bool SWAP, int MC_LOG2, typename GP>
+QFT_HD void tp_pass_b(GP wt, typename Store<DT>::T* Xt, int k) {
+  constexpr int MC = 1 << MC_LOG2;
+  constexpr int N = 8 * MC, h = N / 2, q4 = N / 4, q8 = N / 8;
+  auto dc = wt;
+  auto ds = wt + h;
+  // block N/4 outputs O0 (DCT, k' in [0, N/4)) and O0s (DST, k' in [1, N/4])
+  auto O0 = [&](int kk) -> float2 {
+    const int i = kk >> 1;
+    if ((kk & 1) == 0) return dc[2 * MC + i];
+    const float2 t0 = dc[3 * MC + i];
+    return (i + 1 < MC) ? cadd(t0, (float2)dc[3 * MC + i + 1]) : t0;
+  };
+  auto O0s = [&](int kk) -> float2 {  // DST harmonic kk, stored at position kk-1
+    const int pos = kk - 1, i = pos >> 1;
+    if (pos & 1) return ds[2 * MC + i];
+    const float2 t0 = ds[3 * MC + i];
+    return (i >= 1) ? cadd((float2)ds[3 * MC + i - 1], t0) : t0;
+  };
+  auto put = [&](int kk, float2 C, float2 S) {  // X(kk), X(N-kk) from C(kk), S(kk)
+    Store<DT>::st(Xt, kk, sw<SWAP>(make_float2(C.x + S.y, C.y - S.x)));
+    Store<DT>::st(Xt, N - kk, sw<SWAP>(make_float2(C.x - S.y, C.y + S.x)));
+  };
+  if (k > 0) {
+    // chain level N/2 at k and N/4 - k
+    const float2 E = dc[k], o1 = dc[MC + k];
+    const float2 a = cadd(E, o1), b = csub(E, o1);  // D_{N/2}(k), D_{N/2}(N/4-k)
+    const float2 Es = ds[k], o1s = ds[MC + k - 1];
+    const float2 as = cadd(o1s, Es), bs = csub(o1s, Es);  // S_{N/2}(k), S_{N/2}(N/4-k)
+    // chain level N
+    const float2 ok = O0(k), om = O0(q4 - k);
+    const float2 oks = O0s(k), oms = O0s(q4 - k);
+    put(k, cadd(a, ok), cadd(oks, as));
+    put(h - k, csub(a, ok), csub(oks, as));
+    put(q4 - k, cadd(b, om), cadd(oms, bs));
+    put(q4 + k, csub(b, om), csub(oms, bs));
+  } else {
+    // DCT: D_{N/2}(0), D_{N/2}(N/4), D_{N/2}(N/8) = D_{N/4}(N/8) (top cell)
+    const float2 E0 = dc[0], Et = dc[h], o10 = dc[MC];
+    const float2 a0 = cadd(E0, o10), aq = csub(E0, o10);
+    const float2 o0 = O0(0), o8 = O0(q8);
+    const float2 C0 = cadd(a0, o0), Ch = csub(a0, o0);  // D_N(0), D_N(N/2)
+    const float2 C4 = aq;                               // D_N(N/4) = D_{N/2}(N/4)
+    const float2 C8 = cadd(Et, o8), C38 = csub(Et, o8); // D_N(N/8), D_N(3N/8)
+    // DST: S_{N/2}(N/8) = O1s(N/8); S_N(N/8), S_N(3N/8); S_N(N/4) = O0s(N/4)
+    const float2 s8 = ds[MC + q8 - 1];
+    const float2 o8s = O0s(q8);
+    const float2 S8 = cadd(o8s, s8), S38 = csub(o8s, s8);
+    const float2 S4 = O0s(q4);
+    Store<DT>::st(Xt, 0, sw<SWAP>(C0));
+    Store<DT>::st(Xt, h, sw<SWAP>(Ch));
+    put(q8, C8, S8);
+    put(3 * q8, C38, S38);
+    put(q4, C4, S4);
+  }
+}
+
+// Pass-A workgroups per transform and pass-B threads per transform.
+QFT_HD constexpr int tp_blocks_a() { return 8; }
 
 }  // namespace qftk

@@ -33,20 +33,34 @@ struct DevSync {
   __device__ __forceinline__ void operator()() const { __syncthreads(); }
 };
 
+// Orders the LDS accesses of one wavefront (its lanes exchange data through
+// LDS between chain levels without a workgroup barrier).
+struct DevWaveSync {
+  __device__ __forceinline__ void operator()() const {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+};
+
+constexpr int kWave = 64;
+constexpr int kPad = 3;  // LDS padding: one spare cell per 8 cells
+
 // Tile kernel (uniform batches, N <= 2^TILE_LOG2): T = 2^TILE_LOG2 / N
 // transforms per workgroup.
 template <int TILE_LOG2, int BLOCK, int DT, bool SWAP>
 __global__ __launch_bounds__(BLOCK) void tile_kernel(const typename Store<DT>::T* x,
                                                       typename Store<DT>::T* X, int logn,
                                                       int64_t batch, const float* sec) {
-  __shared__ float2 W[1 << TILE_LOG2];
-  constexpr int MAXI = (1 << TILE_LOG2) / (2 * BLOCK);
+  __shared__ float2 Wl[padded_cells<kPad>(1 << TILE_LOG2)];
+  const PadPtr<kPad> W{Wl, 0};
+  constexpr int CPT = (1 << TILE_LOG2) / BLOCK;
   const int Tmax = 1 << (TILE_LOG2 - logn);
   const int64_t t0 = (int64_t)blockIdx.x * Tmax;
   const int T = (int)min((int64_t)Tmax, batch - t0);
   const int64_t off = t0 << logn;
-  tile_body<DT, SWAP, MAXI>(x + off, X + off, W, logn, T, (const int64_t*)nullptr, sec,
-                            (int)threadIdx.x, BLOCK, DevSync{});
+  tile_body<DT, SWAP, CPT>(x + off, X + off, W, logn, T, (const int64_t*)nullptr, sec,
+                           (int)threadIdx.x, BLOCK, kWave, DevSync{}, DevWaveSync{});
 }
 
 // Persistent kernel for uneven plans: tiles[w] = (logn, first, count, 0)
@@ -59,12 +73,13 @@ __global__ __launch_bounds__(BLOCK) void uneven_kernel(const typename Store<DT>:
                                                         int ntiles,
                                                         const int64_t* __restrict__ offs,
                                                         const float* sec) {
-  __shared__ float2 W[1 << TILE_LOG2];
-  constexpr int MAXI = (1 << TILE_LOG2) / (2 * BLOCK);
+  __shared__ float2 Wl[padded_cells<kPad>(1 << TILE_LOG2)];
+  const PadPtr<kPad> W{Wl, 0};
+  constexpr int CPT = (1 << TILE_LOG2) / BLOCK;
   for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
     const int4 d = tiles[w];
-    tile_body<DT, SWAP, MAXI>(x, X, W, d.x, d.z, offs + d.y, sec, (int)threadIdx.x, BLOCK,
-                              DevSync{});
+    tile_body<DT, SWAP, CPT>(x, X, W, d.x, d.z, offs + d.y, sec, (int)threadIdx.x, BLOCK, kWave,
+                             DevSync{}, DevWaveSync{});
     __syncthreads();
   }
 }
@@ -110,13 +125,47 @@ template <int MC_LOG2, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void mp_segment_kernel(float2* W, int logn,
                                                            const float* sec) {
   constexpr int MC = 1 << MC_LOG2;
-  constexpr int MAXI = (2 * MC) / (2 * BLOCK);
-  __shared__ float2 L[2 * MC];
+  constexpr int CPT = (2 * MC) / BLOCK;
+  __shared__ float2 Ll[padded_cells<kPad>(2 * MC)];
+  const PadPtr<kPad> L{Ll, 0};
   const int per_t = mp_segment_blocks(logn, MC_LOG2);
   const int64_t t = blockIdx.x / per_t;
   const int r = (int)(blockIdx.x - t * per_t);
-  mp_segment_body<MC_LOG2, MAXI>(W + (t << logn), L, logn, r, sec, (int)threadIdx.x, BLOCK,
-                                 DevSync{});
+  mp_segment_body<MC_LOG2, CPT>(W + (t << logn), L, logn, r, sec, (int)threadIdx.x, BLOCK, kWave,
+                                DevSync{}, DevWaveSync{});
+}
+
+// Two-pass path, N = 8 * 2^MC_LOG2.  Pass A: 8 workgroups per transform
+// (side x segment).  Block b serves transform 8*(b/64) + b%8 and workgroup
+// role (b/8)%8, so that the eight workgroups of a transform share b%8, i.e.
+// land on the same XCD (round-robin dispatch) and find x in that XCD's L2.
+template <int MC_LOG2, int BLOCK, int DT, bool SWAP>
+__global__ __launch_bounds__(BLOCK) void tp_a_kernel(const typename Store<DT>::T* x, float2* W,
+                                                      int64_t batch, const float* sec) {
+  constexpr int MC = 1 << MC_LOG2;
+  constexpr int logn = MC_LOG2 + 3;
+  __shared__ float2 Ll[padded_cells<kPad>(MC + 1)];
+  const PadPtr<kPad> L{Ll, 0};
+  constexpr int CPT = MC / BLOCK;
+  const int64_t b = blockIdx.x;
+  const int r = (int)(b & 63);
+  const int64_t t = (b >> 6) * 8 + (r & 7);
+  if (t >= batch) return;
+  tp_pass_a<DT, SWAP, MC_LOG2, CPT>(x + (t << logn), W + (t << logn), L, r >> 3, sec,
+                                    (int)threadIdx.x, BLOCK, kWave, DevSync{}, DevWaveSync{});
+}
+
+template <int MC_LOG2, int DT, bool SWAP>
+__global__ __launch_bounds__(256) void tp_b_kernel(const float2* W, typename Store<DT>::T* X,
+                                                   int64_t batch) {
+  constexpr int logn = MC_LOG2 + 3;
+  const int64_t total = batch << (logn - 3);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * 256) {
+    const int64_t t = i >> (logn - 3);
+    const int k = (int)(i & ((1 << (logn - 3)) - 1));
+    tp_pass_b<DT, SWAP, MC_LOG2>(W + (t << logn), X + (t << logn), k);
+  }
 }
 
 }  // namespace qftk
@@ -327,6 +376,40 @@ qft_status launch_multipass(const void* in, void* out, int log2n, int64_t batch,
   return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
 }
 
+// Two-pass path (N = 2^15, 2^16): pass A into the heap buffer W, pass B to X.
+template <int DT, bool SWAP>
+qft_status launch_twopass(const void* in, void* out, int log2n, int64_t batch, const float* sec,
+                          float2* W, hipStream_t st) {
+  using T = typename qftk::Store<DT>::T;
+  const T* x = (const T*)in;
+  T* X = (T*)out;
+  const int64_t blocks_a = ((batch + 7) / 8) * 64;
+  if (blocks_a > 0x7fffffff) return QFT_ERROR_INVALID_VALUE;
+  const unsigned gb = grid_for(batch << (log2n - 3), 256);
+  if (log2n == 16) {
+    hipLaunchKernelGGL((qftk::tp_a_kernel<13, 512, DT, SWAP>), dim3((unsigned)blocks_a), dim3(512),
+                       0, st, x, W, batch, sec);
+    hipLaunchKernelGGL((qftk::tp_b_kernel<13, DT, SWAP>), dim3(gb), dim3(256), 0, st,
+                       (const float2*)W, X, batch);
+  } else {
+    hipLaunchKernelGGL((qftk::tp_a_kernel<12, 256, DT, SWAP>), dim3((unsigned)blocks_a), dim3(256),
+                       0, st, x, W, batch, sec);
+    hipLaunchKernelGGL((qftk::tp_b_kernel<12, DT, SWAP>), dim3(gb), dim3(256), 0, st,
+                       (const float2*)W, X, batch);
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
+}
+
+// Transforms longer than one workgroup's LDS.
+template <int DT, bool SWAP>
+qft_status launch_large(const void* in, void* out, int log2n, int64_t batch, const float* sec,
+                        float2* W0, float2* W1, hipStream_t st) {
+  if (log2n == 15 || log2n == 16)
+    return launch_twopass<DT, SWAP>(in, out, log2n, batch, sec, W0, st);
+  return launch_multipass<DT, SWAP>(in, out, log2n, batch, sec, W0, W1, st);
+}
+
 template <int DT, bool SWAP>
 qft_status launch_uneven(const qft_plan_s* p, const void* in, void* out, hipStream_t st) {
   using T = typename qftk::Store<DT>::T;
@@ -340,8 +423,8 @@ qft_status launch_uneven(const qft_plan_s* p, const void* in, void* out, hipStre
     if (e != hipSuccess) return hip_fail(e);
   }
   for (const LargeItem& it : p->large) {
-    qft_status s = launch_multipass<DT, SWAP>(x + it.offset, X + it.offset, it.log2n, 1,
-                                              p->d_sec, p->d_work, p->d_work + p->work_cells, st);
+    qft_status s = launch_large<DT, SWAP>(x + it.offset, X + it.offset, it.log2n, 1, p->d_sec,
+                                          p->d_work, p->d_work + p->work_cells, st);
     if (s != QFT_SUCCESS) return s;
   }
   return QFT_SUCCESS;
@@ -370,9 +453,8 @@ qft_status exec_impl(qft_plan_t plan, const void* in, void* out, void* stream) {
   float2* W0 = plan->d_work;
   float2* W1 = plan->d_work + plan->work_cells;
   return plan->dtype == QFT_C32
-             ? launch_multipass<0, SWAP>(in, out, plan->log2n, plan->batch, plan->d_sec, W0, W1, st)
-             : launch_multipass<1, SWAP>(in, out, plan->log2n, plan->batch, plan->d_sec, W0, W1,
-                                         st);
+             ? launch_large<0, SWAP>(in, out, plan->log2n, plan->batch, plan->d_sec, W0, W1, st)
+             : launch_large<1, SWAP>(in, out, plan->log2n, plan->batch, plan->d_sec, W0, W1, st);
 }
 
 }  // namespace

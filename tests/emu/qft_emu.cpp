@@ -78,22 +78,29 @@ struct Ref {
   Ref& operator=(const Ref& r) { return *this = (float2)r; }
 };
 
+// Tracked pointer; with ps > 0 it applies the same padding map as the
+// kernels' LDS pointer (logical cell c at c + (c >> ps)).
 struct TPtr {
   float2* base;
   int64_t off;
   Tracker* tr;
-  int64_t size;  // cells of the buffer starting at base
+  int64_t size;  // logical cells of the buffer starting at base
+  int ps = 0;
   Ref operator[](int64_t i) const {
     static float2 sink;
-    if (off + i < 0 || off + i >= size) {
+    const int64_t c = off + i;
+    if (c < 0 || c >= size) {
       tr->oob++;
       return Ref{&sink, -1, tr};
     }
-    return Ref{base + off + i, (int64_t)(uintptr_t)(base + off + i), tr};
+    const int64_t pc = ps ? c + (c >> ps) : c;
+    return Ref{base + pc, (int64_t)(uintptr_t)(base + pc), tr};
   }
   Ref operator*() const { return (*this)[0]; }
-  TPtr operator+(int64_t d) const { return TPtr{base, off + d, tr, size}; }
+  TPtr operator+(int64_t d) const { return TPtr{base, off + d, tr, size, ps}; }
 };
+
+constexpr int kEmuPad = 3;  // same LDS padding as the GPU kernels
 
 // Runs fn(tid, sync) on nthr threads sharing one barrier whose completion
 // closes a tracker phase.
@@ -117,20 +124,21 @@ void run_workgroup(int nthr, Tracker& tr, F fn) {
   tr.end_phase();
 }
 
-constexpr int kEmuMaxi = 128;
+constexpr int kEmuCpt = 256;  // cells per emulated thread bound (register arrays)
+constexpr int kEmuWave = 32;  // emulated wavefront width (wave-level chain phase)
 
 template <int DT, bool SWAP>
 int tile_impl(const void* x, void* X, int logn, int T, const int64_t* offs, const float* sec,
               int nthr) {
   using E = typename qftk::Store<DT>::T;
   const int64_t cells = (int64_t)T << logn;
-  if ((cells / 2 + nthr - 1) / nthr > kEmuMaxi) return -2;
-  std::vector<float2> lds(cells);
+  if ((cells + nthr - 1) / nthr > kEmuCpt) return -2;
+  std::vector<float2> lds(cells + (cells >> kEmuPad));
   Tracker tr(nthr);
-  TPtr W{lds.data(), 0, &tr, cells};
+  TPtr W{lds.data(), 0, &tr, cells, kEmuPad};
   run_workgroup(nthr, tr, [&](int tid, auto sync) {
-    qftk::tile_body<DT, SWAP, kEmuMaxi>((const E*)x, (E*)X, W, logn, T, offs, sec, tid, nthr,
-                                        sync);
+    qftk::tile_body<DT, SWAP, kEmuCpt>((const E*)x, (E*)X, W, logn, T, offs, sec, tid, nthr,
+                                       kEmuWave, sync, sync);
   });
   return tr.oob ? -100 : (int)tr.races;
 }
@@ -182,12 +190,14 @@ struct EmuMultipass {
     for (int64_t b = 0; b < batch * per_t; ++b) {
       const int64_t t = b / per_t;
       const int r = (int)(b - t * per_t);
-      std::vector<float2> lds((size_t)2 << MC_LOG2);
+      const int64_t lc = (int64_t)2 << MC_LOG2;
+      std::vector<float2> lds(lc + (lc >> kEmuPad));
       Tracker ltr(nthr);
-      TPtr L{lds.data(), 0, &ltr, (int64_t)2 << MC_LOG2};
+      TPtr L{lds.data(), 0, &ltr, lc, kEmuPad};
       float2* wt = cur + (t << logn);
       run_workgroup(nthr, ltr, [&](int tid, auto sync) {
-        qftk::mp_segment_body<MC_LOG2, kEmuMaxi>(wt, L, logn, r, sec, tid, nthr, sync);
+        qftk::mp_segment_body<MC_LOG2, kEmuCpt>(wt, L, logn, r, sec, tid, nthr, kEmuWave, sync,
+                                                sync);
       });
       races += ltr.races;
       if (ltr.oob) races = -1000000;
@@ -256,9 +266,72 @@ int uneven_impl(const void* x, void* X, const int32_t* log2n, int64_t count, int
   return races;
 }
 
+template <int DT, bool SWAP, int MC_LOG2>
+int twopass_mc(const void* x, void* X, int64_t batch, int nthr) {
+  using E = typename qftk::Store<DT>::T;
+  constexpr int MC = 1 << MC_LOG2;
+  constexpr int logn = MC_LOG2 + 3;
+  const int64_t cells = batch << logn;
+  std::vector<float> sec = secants(logn);
+  std::vector<float2> heap(cells, make_float2(0.f, 0.f));
+  int64_t races = 0;
+  // pass A: 8 workgroups per transform
+  for (int64_t t = 0; t < batch; ++t) {
+    for (int w = 0; w < 8; ++w) {
+      const int64_t lc = MC + 1;
+      std::vector<float2> lds(lc + (lc >> kEmuPad));
+      Tracker ltr(nthr);
+      TPtr L{lds.data(), 0, &ltr, lc, kEmuPad};
+      const E* xt = (const E*)x + (t << logn);
+      float2* wt = heap.data() + (t << logn);
+      run_workgroup(nthr, ltr, [&](int tid, auto sync) {
+        qftk::tp_pass_a<DT, SWAP, MC_LOG2, kEmuCpt>(xt, wt, L, w, sec.data(), tid, nthr, kEmuWave,
+                                                    sync, sync);
+      });
+      if (ltr.oob) return -100;
+      races += ltr.races;
+    }
+  }
+  // pass B: N/8 items per transform, tracked reads of the heap buffer
+  Tracker gtr(1);
+  TPtr G{heap.data(), 0, &gtr, cells};
+  tl_slot = 0;
+  for (int64_t t = 0; t < batch; ++t) {
+    for (int k = 0; k < (1 << (logn - 3)); ++k) {
+      tl_actor = t * 100000 + k;
+      qftk::tp_pass_b<DT, SWAP, MC_LOG2>(G + (t << logn), (E*)X + (t << logn), k);
+    }
+  }
+  gtr.end_phase();
+  if (gtr.oob) return -101;
+  return (int)(races + gtr.races);
+}
+
+template <int DT, bool SWAP>
+int twopass_impl(const void* x, void* X, int mc_log2, int64_t batch, int nthr) {
+  switch (mc_log2) {
+    case 3: return twopass_mc<DT, SWAP, 3>(x, X, batch, nthr);
+    case 4: return twopass_mc<DT, SWAP, 4>(x, X, batch, nthr);
+    case 5: return twopass_mc<DT, SWAP, 5>(x, X, batch, nthr);
+    case 7: return twopass_mc<DT, SWAP, 7>(x, X, batch, nthr);
+    case 12: return twopass_mc<DT, SWAP, 12>(x, X, batch, nthr);
+    case 13: return twopass_mc<DT, SWAP, 13>(x, X, batch, nthr);
+    default: return -5;
+  }
+}
+
 }  // namespace
 
 extern "C" {
+
+int emu_twopass(int dt, int swap, const void* x, void* X, int mc_log2, int64_t batch, int nthr) {
+  if (batch < 1 || nthr < 1) return -1;
+  if (dt == 0) return swap ? twopass_impl<0, true>(x, X, mc_log2, batch, nthr)
+                           : twopass_impl<0, false>(x, X, mc_log2, batch, nthr);
+  return swap ? twopass_impl<1, true>(x, X, mc_log2, batch, nthr)
+              : twopass_impl<1, false>(x, X, mc_log2, batch, nthr);
+}
+
 
 int emu_tile(int dt, int swap, const void* x, void* X, int logn, int T, int nthr) {
   if (logn < 1 || logn > 14 || T < 1 || nthr < 1) return -1;

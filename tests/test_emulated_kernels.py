@@ -154,3 +154,33 @@ def test_uneven_worklist(emu):
         err = D.relative_l2(out[off:off + N][None], _ref(seg)).max()
         assert err <= _tol(max(int(r), 1)), (r, err)
         off += N
+
+
+def run_tp(emu, x, mc_log2, nthr=32, swap=0):
+    xf = _as_c64(x)
+    out = np.zeros_like(xf)
+    races = emu.emu_twopass(0, swap, xf.ctypes.data, out.ctypes.data, mc_log2, xf.shape[0], nthr)
+    assert races >= 0, races
+    return races, out
+
+
+@pytest.mark.parametrize("mc_log2", [3, 4, 5, 7])
+@pytest.mark.parametrize("swap", [0, 1])
+def test_two_pass_small(emu, mc_log2, swap):
+    """Two-pass path (N = 8 * segment) with small segments: gather with the
+    fold and the top round from x, per-segment rounds and head chains in LDS,
+    then the streaming top backward round, chain levels N/2 and N, combine."""
+    logn = mc_log2 + 3
+    x = workloads.normal(500 + mc_log2, (3, 1 << logn))
+    races, out = run_tp(emu, x, mc_log2, swap=swap)
+    assert races == 0
+    assert D.relative_l2(out, _ref(x, swap=bool(swap))).max() <= _tol(logn)
+
+
+@pytest.mark.slow
+def test_two_pass_library_size(emu):
+    """N = 2^15 with the library's 2^12-cell segments and 256 threads."""
+    x = workloads.normal(15, (1, 1 << 15))
+    races, out = run_tp(emu, x, 12, nthr=256)
+    assert races == 0
+    assert D.relative_l2(out, _ref(x)).max() <= _tol(15)
