@@ -53,6 +53,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--log2n", type=int, default=16)
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="time a plain device copy of the same bytes instead (for counter "
+                         "calibration and the practical bandwidth ceiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the transform batch is not sharded across "
@@ -78,21 +81,32 @@ def main():
     stream = torch.cuda.current_stream(dev)
     sp = stream.cuda_stream
 
+    def step():
+        if args.calib_copy:
+            yt.copy_(xt)
+        else:
+            qft.qft_exec_fwd(plan.handle, xt.data_ptr(), yt.data_ptr(), sp)
+
     for _ in range(args.warmup):
-        qft.qft_exec_fwd(plan.handle, xt.data_ptr(), yt.data_ptr(), sp)
+        step()
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        qft.qft_exec_fwd(plan.handle, xt.data_ptr(), yt.data_ptr(), sp)
+        step()
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1) / args.steps
 
     info = plan.info
+    if args.calib_copy:
+        nbytes = 2 * xt.numel() * xt.element_size()
+        print(json.dumps({"calibration": "device copy", "bytes_moved": nbytes,
+                          "ms": round(ms, 5), "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}))
+        return
     flop5 = info["flops_5nlogn"]
     gflops = flop5 / (ms * 1e-3) / 1e9
     algo_bytes = info["algo_bytes"]

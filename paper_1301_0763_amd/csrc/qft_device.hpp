@@ -1018,6 +1018,291 @@ QFT_HD int mp_segment_blocks(int logn, int mc_log2) {
 
 
 // ===========================================================================
+// Compile-time specialised sweeps.  Sizes, round schedule and the thread ->
+// group mapping are template parameters, so that index arithmetic folds into
+// LDS instruction offsets and no bounds guards remain.  NS = sides in the
+// buffer (each 2^LGS cells, side s at W + s*2^LGS), NT = threads, MODE as in
+// SideMode (SIDES_ALT: even sides DCT, odd sides DST).
+// ===========================================================================
+template <int A, int B> struct cmin { static constexpr int v = A < B ? A : B; };
+
+template <int K, int S, bool DST, typename SP>
+QFT_HD void fwd_group_s(SP sd, int j, int x, const float* __restrict__ sec, bool skip0) {
+  constexpr int G = S >> K;
+  constexpr int NE = 2 << K;
+  const int base = j * S;
+  float2 e[NE];
+#pragma unroll
+  for (int c = 0; c < (1 << K); ++c) {
+    e[2 * c] = sd[base + c * G + x];
+    e[2 * c + 1] = sd[base + c * G + G - 1 - x];
+  }
+#pragma unroll
+  for (int m = K; m >= 1; --m) {
+    const int span = 1 << m, half = span >> 1;
+    const int L = G << (m - 1);
+    float2 o[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) o[i] = e[i];
+#pragma unroll
+    for (int c0 = 0; c0 < (1 << K); c0 += span) {
+      if (c0 == 0 && skip0 && j == 0) continue;
+#pragma unroll
+      for (int cc = 0; cc < half; ++cc) {
+        const int c = c0 + cc, cm = c0 + span - 1 - cc;
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          const float2 a = e[2 * c + f], b = e[2 * cm + 1 - f];
+          const float hsec = f ? sec[L + cc * G + G - 1 - x] : sec[L + cc * G + x];
+          const float2 sm = cadd(a, b), df = csub(a, b);
+          o[2 * c + f] = DST ? df : sm;
+          o[2 * (c + half) + f] = cscale(DST ? sm : df, hsec);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NE; ++i) e[i] = o[i];
+  }
+#pragma unroll
+  for (int c = 0; c < (1 << K); ++c) {
+    sd[base + c * G + x] = e[2 * c];
+    sd[base + c * G + G - 1 - x] = e[2 * c + 1];
+  }
+}
+
+template <int K, int HI, int LGS, int NS, int NT, int MODE, bool SKIP0, typename WP>
+QFT_HD void fwd_chunk_s(WP W, const float* sec, int tid) {
+  constexpr int lgGroups = LGS - K - 1;
+  constexpr int total = NS << lgGroups;
+  constexpr int NI = (total + NT - 1) / NT;
+  constexpr int lgHalfG = HI - K - 1;
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int i = tid + it * NT;
+    if ((total % NT) != 0 && i >= total) break;
+    const int s = i >> lgGroups;
+    const int g = i & ((1 << lgGroups) - 1);
+    const int j = g >> lgHalfG;
+    const int x = g & ((1 << lgHalfG) - 1);
+    auto sd = W + (s << LGS);
+    if (MODE == SIDES_DST || (MODE == SIDES_ALT && (s & 1)))
+      fwd_group_s<K, (1 << HI), true>(sd, j, x, sec, SKIP0);
+    else
+      fwd_group_s<K, (1 << HI), false>(sd, j, x, sec, SKIP0);
+  }
+}
+
+template <int K, int LGS, int NS, int NT, int MODE, bool SKIP0, typename WP>
+QFT_HD void tail_chunk_s(WP W, const float* sec, int tid) {
+  constexpr int lgGroups = LGS - K;
+  constexpr int total = NS << lgGroups;
+  constexpr int NI = (total + NT - 1) / NT;
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int i = tid + it * NT;
+    if ((total % NT) != 0 && i >= total) break;
+    const int s = i >> lgGroups;
+    const int g = i & ((1 << lgGroups) - 1);
+    auto sd = W + (s << LGS);
+    if (MODE == SIDES_DST || (MODE == SIDES_ALT && (s & 1)))
+      tail_group<K, true>(sd, g, sec, SKIP0);
+    else
+      tail_group<K, false>(sd, g, sec, SKIP0);
+  }
+}
+
+template <int K, int LO, int LGS, int NS, int NT, int MODE, bool SKIP0, class Sync, typename WP>
+QFT_HD void bwd_chunk_s(WP W, int tid, Sync sync) {
+  constexpr int R = 1 << K;
+  constexpr int S = 1 << (LO + K - 1);
+  constexpr int lgG = LO - 1;
+  constexpr int lgGroups = LGS - K;
+  constexpr int total = NS << lgGroups;
+  constexpr int NI = (total + NT - 1) / NT;
+  float2 y[NI][R];
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int i = tid + it * NT;
+    if ((total % NT) != 0 && i >= total) break;
+    const int s = i >> lgGroups;
+    const int g = i & ((1 << lgGroups) - 1);
+    const int j = g >> lgG, ii = g & ((1 << lgG) - 1);
+    auto sd = W + (s << LGS);
+    const bool dst = MODE == SIDES_DST || (MODE == SIDES_ALT && (s & 1));
+    if (SKIP0 && j == 0) {
+      if (dst) bwd_head_load<K, true, 1>(sd, 1 << lgG, ii, y[it]);
+      else bwd_head_load<K, false, 1>(sd, 1 << lgG, ii, y[it]);
+    } else {
+      if (dst) bwd_group_load<K, true>(sd, S, j, ii, y[it]);
+      else bwd_group_load<K, false>(sd, S, j, ii, y[it]);
+    }
+  }
+  sync();
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int i = tid + it * NT;
+    if ((total % NT) != 0 && i >= total) break;
+    const int s = i >> lgGroups;
+    const int g = i & ((1 << lgGroups) - 1);
+    const int j = g >> lgG, ii = g & ((1 << lgG) - 1);
+    auto sd = W + (s << LGS);
+    if (SKIP0 && j == 0) {
+      bwd_head_store<K, 1>(sd, 1 << lgG, ii, y[it]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < R; ++e) sd[j * S + ii * R + e] = y[it][e];
+    }
+  }
+  sync();
+}
+
+// forward chunks for rounds (KT, HI], top down
+template <int HI, int KT, int LGS, int NS, int NT, int MODE, bool SKIP0, class Sync, typename WP>
+QFT_HD void fwd_rounds_s(WP W, const float* sec, int tid, Sync sync) {
+  if constexpr (HI > KT) {
+    constexpr int K = cmin<3, HI - KT>::v;
+    fwd_chunk_s<K, HI, LGS, NS, NT, MODE, SKIP0>(W, sec, tid);
+    sync();
+    fwd_rounds_s<HI - K, KT, LGS, NS, NT, MODE, SKIP0>(W, sec, tid, sync);
+  }
+}
+
+// backward chunks for rounds [LO, TOP], bottom up
+template <int LO, int TOP, int LGS, int NS, int NT, int MODE, bool SKIP0, class Sync, typename WP>
+QFT_HD void bwd_rounds_s(WP W, int tid, Sync sync) {
+  if constexpr (LO <= TOP) {
+    constexpr int K = cmin<3, TOP - LO + 1>::v;
+    bwd_chunk_s<K, LO, LGS, NS, NT, MODE, SKIP0>(W, tid, sync);
+    bwd_rounds_s<LO + K, TOP, LGS, NS, NT, MODE, SKIP0>(W, tid, sync);
+  }
+}
+
+// Forward rounds S = 2^TOP .. 2 and backward rounds back up (TOP >= 1).
+template <int TOP, int LGS, int NS, int NT, int MODE, bool SKIP0, class Sync, typename WP>
+QFT_HD void sweeps_s(WP W, const float* sec, int tid, Sync sync) {
+  if constexpr (TOP >= 1) {
+    constexpr int KT = cmin<3, TOP>::v;
+    fwd_rounds_s<TOP, KT, LGS, NS, NT, MODE, SKIP0>(W, sec, tid, sync);
+    tail_chunk_s<KT, LGS, NS, NT, MODE, SKIP0>(W, sec, tid);
+    sync();
+    bwd_rounds_s<KT + 1, TOP, LGS, NS, NT, MODE, SKIP0>(W, tid, sync);
+  }
+}
+
+// One chain level P = 2^p for T transforms of 2^LOGN cells (closed groups).
+template <int p, int LOGN, int T, int NT, typename WP>
+QFT_HD void chain_level_s(WP W, int tid) {
+  constexpr int per_t = (p <= 2) ? 1 : 1 + 2 * (1 << (p - 3));
+  constexpr int total = T * per_t;
+  constexpr int NI = (total + NT - 1) / NT;
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int i = tid + it * NT;
+    if ((total % NT) != 0 && i >= total) break;
+    const int t = i / per_t;
+    const int g = i - t * per_t;
+    chain_item(W + (t << LOGN), LOGN, p, g);
+  }
+}
+
+template <int p, int PHI, int LOGN, int T, int NT, class Sync, typename WP>
+QFT_HD void chain_levels_s(WP W, int tid, Sync sync) {
+  if constexpr (p <= PHI) {
+    chain_level_s<p, LOGN, T, NT>(W, tid);
+    sync();
+    chain_levels_s<p + 1, PHI, LOGN, T, NT>(W, tid, sync);
+  }
+}
+
+// Chain P = 2 .. 2^LOGN: small levels wave-synchronously (transform t on wave
+// t % waves), the rest with workgroup barriers.
+template <int LOGN, int T, int NT, int WAVE, class Sync, class WSync, typename WP>
+QFT_HD void chain_s(WP W, int tid, Sync sync, WSync wsync) {
+  constexpr int PW = cmin<9, LOGN>::v;
+  constexpr int NW = (NT + WAVE - 1) / WAVE;
+  constexpr int LANES = cmin<NT, WAVE>::v;
+  constexpr int ROUNDS = (T + NW - 1) / NW;
+  const int wave = tid / WAVE, lane = tid - wave * WAVE;
+  for (int r = 0; r < ROUNDS; ++r) {
+    const int t = wave + r * NW;
+#pragma unroll
+    for (int p = 1; p <= PW; ++p) {
+      if (t < T) {
+        const int per_t = chain_groups(p);
+        for (int g = lane; g < per_t; g += LANES) chain_item(W + (t << LOGN), LOGN, p, g);
+      }
+      wsync();
+    }
+  }
+  sync();
+  chain_levels_s<PW + 1, LOGN, LOGN, T, NT>(W, tid, sync);
+}
+
+// Whole tile: T transforms of 2^LOGN points, NT threads (LOGN >= 1).
+template <int DT, bool SWAP, int LOGN, int T, int NT, int WAVE, class Sync, class WSync,
+          typename WP>
+QFT_HD void tile_body_s(const typename Store<DT>::T* x, typename Store<DT>::T* X, WP W, int Tact,
+                        const float* sec, int tid, Sync sync, WSync wsync) {
+  constexpr int n = 1 << LOGN, h = n >> 1;
+  constexpr int total = T << (LOGN - 1);
+  constexpr int FI = (total + NT - 1) / NT;
+  const int tot_act = Tact << (LOGN - 1);
+  float2 av[FI], bv[FI];
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    const int i = tid + it * NT;
+    if (i < tot_act) {
+      const int t = i >> (LOGN - 1);
+      const int m = i & (h - 1);
+      const typename Store<DT>::T* xt = x + ((int64_t)t << LOGN);
+      av[it] = Store<DT>::ld(xt, m);
+      bv[it] = Store<DT>::ld(xt, m == 0 ? h : n - m);
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    const int i = tid + it * NT;
+    if (i < tot_act) {
+      const int t = i >> (LOGN - 1);
+      const int m = i & (h - 1);
+      auto w = W + (t << LOGN);
+      const float2 a = sw<SWAP>(av[it]), b = sw<SWAP>(bv[it]);
+      if (m == 0) {
+        w[0] = a;
+        w[h] = b;
+      } else {
+        const int l = __builtin_ctz(m);
+        const int cell = (n >> (l + 2)) + (m >> (l + 1));
+        w[cell] = cadd(a, b);
+        w[h + cell] = csub(a, b);
+      }
+    }
+  }
+  sync();
+  if constexpr (LOGN >= 3)
+    sweeps_s<LOGN - 2, LOGN - 1, 2 * T, NT, SIDES_ALT, true>(W, sec, tid, sync);
+  chain_s<LOGN, T, NT, WAVE>(W, tid, sync, wsync);
+#pragma unroll
+  for (int it = 0; it < FI; ++it) {
+    const int i = tid + it * NT;
+    if (i < tot_act) {
+      const int t = i >> (LOGN - 1);
+      const int k = i & (h - 1);
+      typename Store<DT>::T* Xt = X + ((int64_t)t << LOGN);
+      auto w = W + (t << LOGN);
+      if (k == 0) {
+        Store<DT>::st(Xt, 0, sw<SWAP>(w[0]));
+        Store<DT>::st(Xt, h, sw<SWAP>(w[h]));
+      } else {
+        const float2 C = w[k], S = w[h + k];
+        Store<DT>::st(Xt, k, sw<SWAP>(make_float2(C.x + S.y, C.y - S.x)));
+        Store<DT>::st(Xt, n - k, sw<SWAP>(make_float2(C.x - S.y, C.y + S.x)));
+      }
+    }
+  }
+}
+
+// ===========================================================================
 // Two-pass path for N = 8 MC, MC = 2^MC_LOG2 (one LDS segment = MC cells).
 // A side has 4 MC cells: segment 0 is the head (blocks < MC, the DCT-0/DST-0
 // chain up to P = 2 MC), segment 1 is the block of size MC, segments 2 and 3
@@ -1083,14 +1368,15 @@ QFT_HD float2 heap_fold_value(const typename Store<DT>::T* xt, int logn, int p) 
 }
 
 // Pass A for one workgroup: w = side * 4 + segment.
-template <int DT, bool SWAP, int MC_LOG2, int CPT, class Sync, class WSync, typename GP,
+template <int DT, bool SWAP, int MC_LOG2, int NT, class Sync, class WSync, typename GP,
           typename LP>
 QFT_HD void tp_pass_a(const typename Store<DT>::T* xt, GP wt, LP L, int w, const float* sec,
-                      int tid, int nthr, int wave_size, Sync sync, WSync wsync) {
+                      int tid, int wave_size, Sync sync, WSync wsync) {
   constexpr int MC = 1 << MC_LOG2;
   constexpr int logn = MC_LOG2 + 3;
   constexpr int N = 1 << logn, h = N >> 1;
-  constexpr int NI = (CPT + 0) > 0 ? CPT : 1;  // cells per thread (MC / nthr)
+  constexpr int NI = MC / NT;  // cells per thread
+  constexpr int nthr = NT;
   const int side = w >> 2, j = w & 3;
   const bool dst = side != 0;
   // ---- gather ----
@@ -1133,13 +1419,17 @@ QFT_HD void tp_pass_a(const typename Store<DT>::T* xt, GP wt, LP L, int w, const
   if (!dst && j == 0 && tid == 0) L[MC] = topv;
   sync();
   // ---- remaining rounds (and the chain for the heads) ----
-  const int mode = dst ? SIDES_DST : SIDES_DCT;
   if (j == 0) {
-    sweeps2<CPT>(L, MC_LOG2, 1, mode, MC_LOG2 - 1, true, sec, tid, nthr, sync);
-    if (dst) chain_one_side<true>(L, L + MC, MC_LOG2 + 1, tid, nthr, wave_size, sync, wsync);
-    else chain_one_side<false>(L, L + MC, MC_LOG2 + 1, tid, nthr, wave_size, sync, wsync);
+    if (dst) {
+      sweeps_s<MC_LOG2 - 1, MC_LOG2, 1, NT, SIDES_DST, true>(L, sec, tid, sync);
+      chain_one_side<true>(L, L + MC, MC_LOG2 + 1, tid, nthr, wave_size, sync, wsync);
+    } else {
+      sweeps_s<MC_LOG2 - 1, MC_LOG2, 1, NT, SIDES_DCT, true>(L, sec, tid, sync);
+      chain_one_side<false>(L, L + MC, MC_LOG2 + 1, tid, nthr, wave_size, sync, wsync);
+    }
   } else {
-    sweeps2<CPT>(L, MC_LOG2, 1, mode, MC_LOG2, false, sec, tid, nthr, sync);
+    if (dst) sweeps_s<MC_LOG2, MC_LOG2, 1, NT, SIDES_DST, false>(L, sec, tid, sync);
+    else sweeps_s<MC_LOG2, MC_LOG2, 1, NT, SIDES_DCT, false>(L, sec, tid, sync);
   }
   // ---- write the segment to the heap buffer ----
   auto seg = wt + (side * h + j * MC);
@@ -1217,5 +1507,82 @@ QFT_HD void tp_pass_b(GP wt, typename Store<DT>::T* Xt, int k) {
 
 // Pass-A workgroups per transform and pass-B threads per transform.
 QFT_HD constexpr int tp_blocks_a() { return 8; }
+
+
+
+
+// Pass A with both sides of one segment index j in the same workgroup: the
+// DCT and DST cells of a position come from the same x samples (c = a + b,
+// d = a - b), so x is gathered once for both.  LDS: DCT segment at L[0, MC),
+// DST segment at L[MC, 2MC), the DCT top cell (c(N/2) / D(MC)) at L[2MC].
+template <int DT, bool SWAP, int MC_LOG2, int NT, class Sync, class WSync, typename GP,
+          typename LP>
+QFT_HD void tp_pass_a2(const typename Store<DT>::T* xt, GP wt, LP L, int j, const float* sec,
+                       int tid, int wave_size, Sync sync, WSync wsync) {
+  constexpr int MC = 1 << MC_LOG2;
+  constexpr int logn = MC_LOG2 + 3;
+  constexpr int N = 1 << logn, h = N >> 1;
+  constexpr int NI = MC / NT;  // positions per thread
+  float2 vc[NI], vs[NI];
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int q = tid + it * NT;
+    const int p = j * MC + q;
+    if (j < 2) {
+      if (p == 0) {
+        vc[it] = sw<SWAP>(Store<DT>::ld(xt, 0));  // c(0)
+        vs[it] = make_float2(0.f, 0.f);           // (DST cell 0 holds the top)
+      } else {
+        const int lgM = 31 - __builtin_clz(p);
+        const int v = p - (1 << lgM);
+        const int n = (2 * v + 1) << (logn - 2 - lgM);
+        const float2 a = sw<SWAP>(Store<DT>::ld(xt, n));
+        const float2 b = sw<SWAP>(Store<DT>::ld(xt, N - n));
+        vc[it] = cadd(a, b);
+        vs[it] = csub(a, b);
+      }
+    } else {
+      const int n = 2 * q + 1;
+      const float2 a0 = sw<SWAP>(Store<DT>::ld(xt, n));
+      const float2 b0 = sw<SWAP>(Store<DT>::ld(xt, N - n));
+      const float2 a1 = sw<SWAP>(Store<DT>::ld(xt, h - n));
+      const float2 b1 = sw<SWAP>(Store<DT>::ld(xt, h + n));
+      const float2 c0 = cadd(a0, b0), c1 = cadd(a1, b1);  // c(n), c(N/2-n)
+      const float2 d0 = csub(a0, b0), d1 = csub(a1, b1);  // d(n), d(N/2-n)
+      if (j == 2) {
+        vc[it] = cadd(c0, c1);
+        vs[it] = csub(d0, d1);
+      } else {
+        const float hs = sec[MC + q];
+        vc[it] = cscale(csub(c0, c1), hs);
+        vs[it] = cscale(cadd(d0, d1), hs);
+      }
+    }
+  }
+  float2 topv = make_float2(0.f, 0.f);
+  if (j == 0 && tid == 0) topv = sw<SWAP>(Store<DT>::ld(xt, h));  // c(N/2)
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int q = tid + it * NT;
+    L[q] = vc[it];
+    L[MC + q] = vs[it];
+  }
+  if (j == 0 && tid == 0) L[2 * MC] = topv;
+  sync();
+  if (j == 0) {
+    sweeps_s<MC_LOG2 - 1, MC_LOG2, 2, NT, SIDES_ALT, true>(L, sec, tid, sync);
+    chain_one_side<false>(L, L + 2 * MC, MC_LOG2 + 1, tid, NT, wave_size, sync, wsync);
+    chain_one_side<true>(L + MC, L + 2 * MC, MC_LOG2 + 1, tid, NT, wave_size, sync, wsync);
+  } else {
+    sweeps_s<MC_LOG2, MC_LOG2, 2, NT, SIDES_ALT, false>(L, sec, tid, sync);
+  }
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int q = tid + it * NT;
+    wt[j * MC + q] = (float2)L[q];
+    if (!(j == 0 && q == 0)) wt[h + j * MC + q] = (float2)L[MC + q];
+  }
+  if (j == 0 && tid == 0) wt[h] = (float2)L[2 * MC];  // D_{2MC}(MC): top cell
+}
 
 }  // namespace qftk

@@ -46,21 +46,19 @@ struct DevWaveSync {
 constexpr int kWave = 64;
 constexpr int kPad = 3;  // LDS padding: one spare cell per 8 cells
 
-// Tile kernel (uniform batches, N <= 2^TILE_LOG2): T = 2^TILE_LOG2 / N
-// transforms per workgroup.
-template <int TILE_LOG2, int BLOCK, int DT, bool SWAP>
-__global__ __launch_bounds__(BLOCK) void tile_kernel(const typename Store<DT>::T* x,
-                                                      typename Store<DT>::T* X, int logn,
-                                                      int64_t batch, const float* sec) {
+// Specialised tile kernel: T = 2^(TILE_LOG2 - LOGN) transforms of 2^LOGN.
+template <int LOGN, int TILE_LOG2, int BLOCK, int DT, bool SWAP>
+__global__ __launch_bounds__(BLOCK) void tile_kernel_s(const typename Store<DT>::T* x,
+                                                        typename Store<DT>::T* X, int64_t batch,
+                                                        const float* sec) {
+  constexpr int T = 1 << (TILE_LOG2 - LOGN);
   __shared__ float2 Wl[padded_cells<kPad>(1 << TILE_LOG2)];
   const PadPtr<kPad> W{Wl, 0};
-  constexpr int CPT = (1 << TILE_LOG2) / BLOCK;
-  const int Tmax = 1 << (TILE_LOG2 - logn);
-  const int64_t t0 = (int64_t)blockIdx.x * Tmax;
-  const int T = (int)min((int64_t)Tmax, batch - t0);
-  const int64_t off = t0 << logn;
-  tile_body<DT, SWAP, CPT>(x + off, X + off, W, logn, T, (const int64_t*)nullptr, sec,
-                           (int)threadIdx.x, BLOCK, kWave, DevSync{}, DevWaveSync{});
+  const int64_t t0 = (int64_t)blockIdx.x * T;
+  const int Tact = (int)min((int64_t)T, batch - t0);
+  const int64_t off = t0 << LOGN;
+  tile_body_s<DT, SWAP, LOGN, T, BLOCK, kWave>(x + off, X + off, W, Tact, sec, (int)threadIdx.x,
+                                               DevSync{}, DevWaveSync{});
 }
 
 // Persistent kernel for uneven plans: tiles[w] = (logn, first, count, 0)
@@ -146,13 +144,29 @@ __global__ __launch_bounds__(BLOCK) void tp_a_kernel(const typename Store<DT>::T
   constexpr int logn = MC_LOG2 + 3;
   __shared__ float2 Ll[padded_cells<kPad>(MC + 1)];
   const PadPtr<kPad> L{Ll, 0};
-  constexpr int CPT = MC / BLOCK;
   const int64_t b = blockIdx.x;
   const int r = (int)(b & 63);
   const int64_t t = (b >> 6) * 8 + (r & 7);
   if (t >= batch) return;
-  tp_pass_a<DT, SWAP, MC_LOG2, CPT>(x + (t << logn), W + (t << logn), L, r >> 3, sec,
-                                    (int)threadIdx.x, BLOCK, kWave, DevSync{}, DevWaveSync{});
+  tp_pass_a<DT, SWAP, MC_LOG2, BLOCK>(x + (t << logn), W + (t << logn), L, r >> 3, sec,
+                                      (int)threadIdx.x, kWave, DevSync{}, DevWaveSync{});
+}
+
+// Pass A with both sides per workgroup: 4 workgroups per transform, block b
+// serves transform 8*(b/32) + b%8 and segment (b/8)%4 (same XCD per transform).
+template <int MC_LOG2, int BLOCK, int DT, bool SWAP>
+__global__ __launch_bounds__(BLOCK) void tp_a2_kernel(const typename Store<DT>::T* x, float2* W,
+                                                       int64_t batch, const float* sec) {
+  constexpr int MC = 1 << MC_LOG2;
+  constexpr int logn = MC_LOG2 + 3;
+  __shared__ float2 Ll[padded_cells<kPad>(2 * MC + 1)];
+  const PadPtr<kPad> L{Ll, 0};
+  const int64_t b = blockIdx.x;
+  const int r = (int)(b & 31);
+  const int64_t t = (b >> 5) * 8 + (r & 7);
+  if (t >= batch) return;
+  tp_pass_a2<DT, SWAP, MC_LOG2, BLOCK>(x + (t << logn), W + (t << logn), L, r >> 3, sec,
+                                       (int)threadIdx.x, kWave, DevSync{}, DevWaveSync{});
 }
 
 template <int MC_LOG2, int DT, bool SWAP>
@@ -291,25 +305,31 @@ inline unsigned grid_for(int64_t work, int block) {
   return (unsigned)g;
 }
 
+template <int LOGN, int DT, bool SWAP>
+void launch_tile_s(const void* in, void* out, int64_t batch, const float* sec, hipStream_t st) {
+  using T = typename qftk::Store<DT>::T;
+  constexpr int TL = LOGN <= 12 ? 12 : LOGN;
+  constexpr int BLOCK = TL == 12 ? 256 : (TL == 13 ? 512 : 1024);
+  constexpr int64_t Tmax = (int64_t)1 << (TL - LOGN);
+  const int64_t grid = (batch + Tmax - 1) / Tmax;
+  hipLaunchKernelGGL((qftk::tile_kernel_s<LOGN, TL, BLOCK, DT, SWAP>), dim3((unsigned)grid),
+                     dim3(BLOCK), 0, st, (const T*)in, (T*)out, batch, sec);
+}
+
 template <int DT, bool SWAP>
 qft_status launch_tile(const void* in, void* out, int log2n, int64_t batch, const float* sec,
                        hipStream_t st) {
-  using T = typename qftk::Store<DT>::T;
-  const T* x = (const T*)in;
-  T* X = (T*)out;
-  int tl = log2n <= 12 ? 12 : log2n;
-  const int64_t Tmax = (int64_t)1 << (tl - log2n);
-  const int64_t grid = (batch + Tmax - 1) / Tmax;
-  if (grid > 0x7fffffff) return QFT_ERROR_INVALID_VALUE;
-  if (tl == 12) {
-    hipLaunchKernelGGL((qftk::tile_kernel<12, 256, DT, SWAP>), dim3((unsigned)grid), dim3(256), 0,
-                       st, x, X, log2n, batch, sec);
-  } else if (tl == 13) {
-    hipLaunchKernelGGL((qftk::tile_kernel<13, 512, DT, SWAP>), dim3((unsigned)grid), dim3(512), 0,
-                       st, x, X, log2n, batch, sec);
-  } else {
-    hipLaunchKernelGGL((qftk::tile_kernel<14, 1024, DT, SWAP>), dim3((unsigned)grid), dim3(1024),
-                       0, st, x, X, log2n, batch, sec);
+  const int tl = log2n <= 12 ? 12 : log2n;
+  if (((batch + ((int64_t)1 << (tl - log2n)) - 1) >> (tl - log2n)) > 0x7fffffff)
+    return QFT_ERROR_INVALID_VALUE;
+  switch (log2n) {
+#define QFT_TILE_CASE(L) \
+  case L: launch_tile_s<L, DT, SWAP>(in, out, batch, sec, st); break;
+    QFT_TILE_CASE(1) QFT_TILE_CASE(2) QFT_TILE_CASE(3) QFT_TILE_CASE(4) QFT_TILE_CASE(5)
+    QFT_TILE_CASE(6) QFT_TILE_CASE(7) QFT_TILE_CASE(8) QFT_TILE_CASE(9) QFT_TILE_CASE(10)
+    QFT_TILE_CASE(11) QFT_TILE_CASE(12) QFT_TILE_CASE(13) QFT_TILE_CASE(14)
+#undef QFT_TILE_CASE
+    default: return QFT_ERROR_INVALID_SIZE;
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
@@ -387,13 +407,13 @@ qft_status launch_twopass(const void* in, void* out, int log2n, int64_t batch, c
   if (blocks_a > 0x7fffffff) return QFT_ERROR_INVALID_VALUE;
   const unsigned gb = grid_for(batch << (log2n - 3), 256);
   if (log2n == 16) {
-    hipLaunchKernelGGL((qftk::tp_a_kernel<13, 512, DT, SWAP>), dim3((unsigned)blocks_a), dim3(512),
-                       0, st, x, W, batch, sec);
+    hipLaunchKernelGGL((qftk::tp_a2_kernel<13, 1024, DT, SWAP>), dim3((unsigned)(blocks_a / 2)),
+                       dim3(1024), 0, st, x, W, batch, sec);
     hipLaunchKernelGGL((qftk::tp_b_kernel<13, DT, SWAP>), dim3(gb), dim3(256), 0, st,
                        (const float2*)W, X, batch);
   } else {
-    hipLaunchKernelGGL((qftk::tp_a_kernel<12, 256, DT, SWAP>), dim3((unsigned)blocks_a), dim3(256),
-                       0, st, x, W, batch, sec);
+    hipLaunchKernelGGL((qftk::tp_a2_kernel<12, 512, DT, SWAP>), dim3((unsigned)(blocks_a / 2)),
+                       dim3(512), 0, st, x, W, batch, sec);
     hipLaunchKernelGGL((qftk::tp_b_kernel<12, DT, SWAP>), dim3(gb), dim3(256), 0, st,
                        (const float2*)W, X, batch);
   }

@@ -156,31 +156,67 @@ def test_uneven_worklist(emu):
         off += N
 
 
-def run_tp(emu, x, mc_log2, nthr=32, swap=0):
+def run_tp(emu, x, mc_log2, variant=1, swap=0):
+    """variant 0: one side per pass-A workgroup; 1: both sides (as launched)."""
     xf = _as_c64(x)
     out = np.zeros_like(xf)
-    races = emu.emu_twopass(0, swap, xf.ctypes.data, out.ctypes.data, mc_log2, xf.shape[0], nthr)
+    races = emu.emu_twopass(0, swap, xf.ctypes.data, out.ctypes.data, mc_log2, xf.shape[0],
+                            variant)
     assert races >= 0, races
     return races, out
 
 
 @pytest.mark.parametrize("mc_log2", [3, 4, 5, 7])
 @pytest.mark.parametrize("swap", [0, 1])
-def test_two_pass_small(emu, mc_log2, swap):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_two_pass_small(emu, mc_log2, swap, variant):
     """Two-pass path (N = 8 * segment) with small segments: gather with the
     fold and the top round from x, per-segment rounds and head chains in LDS,
     then the streaming top backward round, chain levels N/2 and N, combine."""
     logn = mc_log2 + 3
     x = workloads.normal(500 + mc_log2, (3, 1 << logn))
-    races, out = run_tp(emu, x, mc_log2, swap=swap)
+    races, out = run_tp(emu, x, mc_log2, variant=variant, swap=swap)
     assert races == 0
     assert D.relative_l2(out, _ref(x, swap=bool(swap))).max() <= _tol(logn)
 
 
 @pytest.mark.slow
 def test_two_pass_library_size(emu):
-    """N = 2^15 with the library's 2^12-cell segments and 256 threads."""
+    """N = 2^15 with the library's 2^12-cell segments (512 threads, both sides
+    per workgroup, as launched)."""
     x = workloads.normal(15, (1, 1 << 15))
-    races, out = run_tp(emu, x, 12, nthr=256)
+    races, out = run_tp(emu, x, 12, variant=1)
     assert races == 0
     assert D.relative_l2(out, _ref(x)).max() <= _tol(15)
+
+
+@pytest.mark.parametrize("logn", range(1, 15))
+def test_specialised_tile_as_launched(emu, logn):
+    """The compile-time specialised tile kernel with the GPU's own tile size
+    and thread count (2^12-cell tiles of 256 threads up to N = 2^12, then
+    512 and 1024 threads), on a full tile and on a ragged last tile."""
+    N = 1 << logn
+    T = max(1, 4096 // N) if logn <= 12 else 1
+    for Tact in sorted({T, max(1, T // 2 - 1)}):
+        x = workloads.uniform(700 + logn + Tact, (Tact, N))
+        xf = _as_c64(x)
+        out = np.zeros_like(xf)
+        races = emu.emu_tile_s(0, 0, xf.ctypes.data, out.ctypes.data, logn, Tact)
+        assert races == 0, races
+        assert D.relative_l2(out, _ref(x)).max() <= _tol(max(logn, 1))
+
+
+@pytest.mark.parametrize("logn", [2, 9, 13])
+def test_specialised_tile_adjoint_and_fp16(emu, logn):
+    N = 1 << logn
+    x = workloads.uniform(800 + logn, (1, N))
+    xf = _as_c64(x)
+    out = np.zeros_like(xf)
+    assert emu.emu_tile_s(0, 1, xf.ctypes.data, out.ctypes.data, logn, 1) == 0
+    assert D.relative_l2(out, _ref(x, swap=True)).max() <= _tol(logn)
+    x16 = np.stack([x.real, x.imag], -1).astype(np.float16)
+    o16 = np.zeros_like(x16)
+    assert emu.emu_tile_s(1, 0, x16.ctypes.data, o16.ctypes.data, logn, 1) == 0
+    xin = x16[..., 0].astype(np.float64) + 1j * x16[..., 1].astype(np.float64)
+    got = o16[..., 0].astype(np.float64) + 1j * o16[..., 1].astype(np.float64)
+    assert D.relative_l2(got, Q.qft(xin)).max() < 1e-3
