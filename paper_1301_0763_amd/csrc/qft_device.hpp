@@ -1156,11 +1156,19 @@ QFT_HD void bwd_chunk_s(WP W, int tid, Sync sync) {
   sync();
 }
 
+// Rounds per LDS pass (KC) and fused innermost rounds (KT).
+#ifndef QFT_KC
+#define QFT_KC 3
+#endif
+#ifndef QFT_KT
+#define QFT_KT 3
+#endif
+
 // forward chunks for rounds (KT, HI], top down
 template <int HI, int KT, int LGS, int NS, int NT, int MODE, bool SKIP0, class Sync, typename WP>
 QFT_HD void fwd_rounds_s(WP W, const float* sec, int tid, Sync sync) {
   if constexpr (HI > KT) {
-    constexpr int K = cmin<3, HI - KT>::v;
+    constexpr int K = cmin<QFT_KC, HI - KT>::v;
     fwd_chunk_s<K, HI, LGS, NS, NT, MODE, SKIP0>(W, sec, tid);
     sync();
     fwd_rounds_s<HI - K, KT, LGS, NS, NT, MODE, SKIP0>(W, sec, tid, sync);
@@ -1171,7 +1179,7 @@ QFT_HD void fwd_rounds_s(WP W, const float* sec, int tid, Sync sync) {
 template <int LO, int TOP, int LGS, int NS, int NT, int MODE, bool SKIP0, class Sync, typename WP>
 QFT_HD void bwd_rounds_s(WP W, int tid, Sync sync) {
   if constexpr (LO <= TOP) {
-    constexpr int K = cmin<3, TOP - LO + 1>::v;
+    constexpr int K = cmin<QFT_KC, TOP - LO + 1>::v;
     bwd_chunk_s<K, LO, LGS, NS, NT, MODE, SKIP0>(W, tid, sync);
     bwd_rounds_s<LO + K, TOP, LGS, NS, NT, MODE, SKIP0>(W, tid, sync);
   }
@@ -1181,7 +1189,7 @@ QFT_HD void bwd_rounds_s(WP W, int tid, Sync sync) {
 template <int TOP, int LGS, int NS, int NT, int MODE, bool SKIP0, class Sync, typename WP>
 QFT_HD void sweeps_s(WP W, const float* sec, int tid, Sync sync) {
   if constexpr (TOP >= 1) {
-    constexpr int KT = cmin<3, TOP>::v;
+    constexpr int KT = cmin<QFT_KT, TOP>::v;
     fwd_rounds_s<TOP, KT, LGS, NS, NT, MODE, SKIP0>(W, sec, tid, sync);
     tail_chunk_s<KT, LGS, NS, NT, MODE, SKIP0>(W, sec, tid);
     sync();

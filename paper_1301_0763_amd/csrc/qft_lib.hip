@@ -44,7 +44,10 @@ struct DevWaveSync {
 };
 
 constexpr int kWave = 64;
-constexpr int kPad = 3;  // LDS padding: one spare cell per 8 cells
+#ifndef QFT_PAD
+#define QFT_PAD 3
+#endif
+constexpr int kPad = QFT_PAD;  // LDS padding: one spare cell per 2^kPad cells
 
 // Specialised tile kernel: T = 2^(TILE_LOG2 - LOGN) transforms of 2^LOGN.
 template <int LOGN, int TILE_LOG2, int BLOCK, int DT, bool SWAP>
