@@ -35,7 +35,8 @@ def load():
     L.emu_multipass.argtypes = [i, i, vp, vp, i, i64, i, i]
     L.emu_uneven.argtypes = [i, i, vp, vp, ctypes.POINTER(ctypes.c_int32), i64, i, i, i]
     L.emu_twopass.argtypes = [i, i, vp, vp, i, i64, i]
-    for f in (L.emu_tile, L.emu_multipass, L.emu_uneven, L.emu_twopass):
+    L.emu_tile_s.argtypes = [i, i, vp, vp, i, i]
+    for f in (L.emu_tile, L.emu_multipass, L.emu_uneven, L.emu_twopass, L.emu_tile_s):
         f.restype = i
     return L
 

@@ -247,3 +247,44 @@ def test_plan_info():
     assert info["algo_bytes"] == 2 * 256 * 65536 * 8
     assert info["flops_actual"] == 256 * (4 * 65536 * 16 - 6 * 65536 + 8)
     p.close()
+
+
+@pytest.mark.parametrize("kind", ["uneven", "two_pass", "tile"])
+def test_graph_capture_replays(kind):
+    """exec neither allocates nor issues memsets, so it can be captured in a
+    HIP graph (torch.cuda.CUDAGraph).  The graph is replayed several times with
+    the program's own eager work and synchronisations in between, and every
+    replay must equal the eager result bit for bit."""
+    say(f"graph capture: {kind}")
+    if kind == "uneven":
+        r, vals = workloads.make("c4")
+        x = torch.from_numpy(vals).to(DEV)
+        plan = qft.UnevenPlan(r.tolist())
+    elif kind == "two_pass":
+        x = torch.from_numpy(workloads.normal(77, (8, 1 << 16))).to(DEV)
+        plan = qft.Plan(16, 8)
+    else:
+        x = torch.from_numpy(workloads.uniform(78, (64, 1 << 10))).to(DEV)
+        plan = qft.Plan(10, 64)
+    eager = plan.forward(x)
+    torch.cuda.synchronize()
+    out = torch.empty_like(x)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.forward(x, out)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        qft.qft_exec_fwd(plan.handle, x.data_ptr(), out.data_ptr(),
+                         torch.cuda.current_stream().cuda_stream)
+    for rep in range(4):
+        out.zero_()
+        junk = (x * (rep + 1)).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), f"replay {rep} differs"
+        del junk
+    plan.close()
