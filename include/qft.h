@@ -77,10 +77,12 @@ qft_status qft_plan_create(qft_plan_t* plan, int log2n, int64_t batch, qft_dtype
 /*
  * Plan for `count` transforms of possibly different lengths 2^log2n[i]
  * (host array, read during the call only), packed back to back in the given
- * order.  Every log2n[i] must lie in [1, QFT_MAX_LOG2N]; transforms longer
- * than one workgroup's local memory are handled by the multi-pass path.  The
- * plan builds a size-sorted work list and runs all transforms that fit in
- * local memory in one persistent launch.
+ * order.  Every log2n[i] must lie in [1, QFT_MAX_LOG2N].  Transforms of up to
+ * 2^14 points run in persistent tile-kernel launches over size-sorted work
+ * lists (whole transforms in one workgroup's local memory); longer ones use
+ * the two-pass (2^15, 2^16) or multi-pass path, one after the other.  The
+ * plan holds several schedules (see qft_plan_schedules); schedule 0 runs
+ * every transform of up to 2^14 points in ONE persistent launch.
  */
 qft_status qft_plan_create_uneven(qft_plan_t* plan, const int32_t* log2n, int64_t count,
                                   qft_dtype dtype, int device);
@@ -110,6 +112,41 @@ qft_status qft_plan_destroy(qft_plan_t plan);
  */
 qft_status qft_plan_info(qft_plan_t plan, int64_t* total_points, int64_t* algo_bytes,
                          double* flops_5nlogn, double* flops_actual);
+
+/*
+ * Schedules.  A plan holds one or more schedules, each a list of persistent
+ * tile-kernel launches ("groups") that says which transform sizes run with
+ * which tile size: tiles of 2^12 cells (256 threads, 4 workgroups per CU),
+ * 2^13 (512 threads, 2 per CU) or 2^14 (1024 threads, 1 per CU), and how
+ * the launch covers its tiles: a resident grid whose workgroups stride over
+ * the tile list (persistent), or one workgroup per tile (name suffix
+ * "/all").  Uniform plans with N <= 2^14 have one schedule per tile size
+ * that holds a transform and grid policy (persistent, smallest tile first,
+ * is the default); uneven plans have the tile-size assignments for
+ * N <= 2^12, 2^13, 2^14 of {14,14,14}, {13,13,14}, {12,14,14}, {12,13,14}
+ * (duplicates removed), each persistent and "/all"; schedule 0, the default,
+ * runs every transform of up to 2^14 points in one persistent launch.  All
+ * schedules compute the same result, bit for bit.
+ *
+ * qft_plan_schedules: number of schedules and the one exec uses.
+ * qft_plan_schedule_name: a static description such as "t12:6-12+t14:13-14"
+ *   (tile size : range of log2n per launch), valid until the plan is
+ *   destroyed; NULL for a bad plan or index.
+ * qft_plan_set_schedule: selects the schedule exec uses (e.g. a stored
+ *   autotuning result); QFT_ERROR_INVALID_VALUE for a bad index.
+ * qft_plan_autotune: runs every schedule once to warm up and then `reps`
+ *   times (1..10000), timed with HIP events on `stream`, selects the fastest
+ *   and returns its index in *chosen (may be NULL); ms[i], i < ms_len, gets
+ *   the mean time of schedule i in milliseconds (ms may be NULL when
+ *   ms_len = 0).  It overwrites `out` with F in (in is left unchanged unless
+ *   in == out), synchronises the stream and must not be called during graph
+ *   capture or while another exec of the plan is in flight.
+ */
+qft_status qft_plan_schedules(qft_plan_t plan, int* count, int* chosen);
+const char* qft_plan_schedule_name(qft_plan_t plan, int schedule);
+qft_status qft_plan_set_schedule(qft_plan_t plan, int schedule);
+qft_status qft_plan_autotune(qft_plan_t plan, const void* in, void* out, void* stream, int reps,
+                             double* ms, int ms_len, int* chosen);
 
 /*
  * Host-only (no GPU needed): writes the FP32 constant table used for

@@ -17,14 +17,17 @@ import threading
 
 from . import _lib
 from ._lib import (QFT_C16, QFT_C32, QFT_MAX_LOG2N, QFTError, qft_exec_bwd, qft_exec_fwd,
-                   qft_last_hip_error, qft_plan_create, qft_plan_create_uneven,
-                   qft_plan_destroy, qft_plan_info, qft_secant_table, qft_status_string)
+                   qft_last_hip_error, qft_plan_autotune, qft_plan_create,
+                   qft_plan_create_uneven, qft_plan_destroy, qft_plan_info,
+                   qft_plan_schedule_name, qft_plan_schedules, qft_plan_set_schedule,
+                   qft_secant_table, qft_status_string)
 
 __all__ = [
     "Plan", "UnevenPlan", "fft", "fft_adjoint", "fft_packed", "QFTFunction", "QFTError",
     "qft_plan_create", "qft_plan_create_uneven", "qft_exec_fwd", "qft_exec_bwd",
     "qft_plan_destroy", "qft_plan_info", "qft_secant_table", "qft_status_string",
-    "qft_last_hip_error", "QFT_C32", "QFT_C16", "QFT_MAX_LOG2N",
+    "qft_last_hip_error", "qft_plan_schedules", "qft_plan_schedule_name",
+    "qft_plan_set_schedule", "qft_plan_autotune", "QFT_C32", "QFT_C16", "QFT_MAX_LOG2N",
 ]
 
 
@@ -84,6 +87,31 @@ class Plan:
         self._check(X, out)
         qft_exec_bwd(self.handle, X.data_ptr(), out.data_ptr(), _stream_ptr(X.device))
         return out
+
+    @property
+    def schedules(self):
+        """Names of the plan's schedules (index = schedule number)."""
+        n, _ = qft_plan_schedules(self.handle)
+        return [qft_plan_schedule_name(self.handle, i) for i in range(n)]
+
+    @property
+    def schedule(self):
+        """Index of the schedule exec uses."""
+        return qft_plan_schedules(self.handle)[1]
+
+    @schedule.setter
+    def schedule(self, index):
+        qft_plan_set_schedule(self.handle, index)
+
+    def autotune(self, x, out=None, reps=10):
+        """Times every schedule on x (result written to out) and keeps the
+        fastest; returns {name: ms}.  Synchronises the current stream."""
+        torch = _torch()
+        out = torch.empty_like(x) if out is None else out
+        self._check(x, out)
+        _, ms = qft_plan_autotune(self.handle, x.data_ptr(), out.data_ptr(),
+                                  _stream_ptr(x.device), reps)
+        return dict(zip(self.schedules, ms))
 
     def close(self):
         if self.handle:

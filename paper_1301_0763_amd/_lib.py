@@ -57,9 +57,16 @@ def lib():
         L.qft_status_string.argtypes = [i32]
         L.qft_status_string.restype = ctypes.c_char_p
         L.qft_last_hip_error.argtypes = []
+        L.qft_plan_schedules.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.qft_plan_schedule_name.argtypes = [vp, i32]
+        L.qft_plan_schedule_name.restype = ctypes.c_char_p
+        L.qft_plan_set_schedule.argtypes = [vp, i32]
+        L.qft_plan_autotune.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(ctypes.c_double), i32,
+                                        ctypes.POINTER(i32)]
         for f in ("qft_plan_create", "qft_plan_create_uneven", "qft_exec_fwd", "qft_exec_bwd",
                   "qft_plan_destroy", "qft_plan_info", "qft_secant_table",
-                  "qft_last_hip_error"):
+                  "qft_last_hip_error", "qft_plan_schedules", "qft_plan_set_schedule",
+                  "qft_plan_autotune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -121,3 +128,32 @@ def qft_secant_table(log2n_max):
     buf = (ctypes.c_float * n)()
     _check(lib().qft_secant_table(buf, int(log2n_max)), "qft_secant_table")
     return buf
+
+
+def qft_plan_schedules(plan):
+    """(number of schedules, index exec uses)."""
+    n, c = ctypes.c_int(), ctypes.c_int()
+    _check(lib().qft_plan_schedules(plan, ctypes.byref(n), ctypes.byref(c)),
+           "qft_plan_schedules")
+    return n.value, c.value
+
+
+def qft_plan_schedule_name(plan, schedule):
+    name = lib().qft_plan_schedule_name(plan, int(schedule))
+    if name is None:
+        raise QFTError(QFT_ERROR_INVALID_VALUE, "qft_plan_schedule_name")
+    return name.decode()
+
+
+def qft_plan_set_schedule(plan, schedule):
+    _check(lib().qft_plan_set_schedule(plan, int(schedule)), "qft_plan_set_schedule")
+
+
+def qft_plan_autotune(plan, in_ptr, out_ptr, stream=0, reps=10):
+    """Times every schedule; returns (chosen index, [ms per schedule])."""
+    n, _ = qft_plan_schedules(plan)
+    ms = (ctypes.c_double * max(n, 1))()
+    chosen = ctypes.c_int()
+    _check(lib().qft_plan_autotune(plan, in_ptr, out_ptr, stream, int(reps), ms, n,
+                                   ctypes.byref(chosen)), "qft_plan_autotune")
+    return chosen.value, [ms[i] for i in range(n)]

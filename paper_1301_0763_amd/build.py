@@ -1,4 +1,11 @@
-"""Builds the gfx950 library ``libqft.so`` in-tree from ``csrc/qft_lib.hip``.
+"""Builds the gfx950 library ``libqft.so`` in-tree.
+
+Thirteen translation units compile in parallel (at most MAX_JOBS or one per
+CPU at a time) and link into one shared library: ``csrc/qft_lib.hip``
+(plans, C ABI, two-pass and multi-pass kernels) and ``csrc/qft_tiles.hip``
+once per storage type (``-DQFT_TILE_DT=0`` complex FP32, ``=1`` complex
+FP16), tile size (``-DQFT_TILE_TL=12, 13, 14``) and direction
+(``-DQFT_TILE_SWAP=0`` forward, ``=1`` adjoint).
 
 Flags: ``--offload-arch=gfx950 -O3`` and packed FP32 instructions disabled
 (``-Xclang -target-feature -Xclang -packed-fp32-ops``; the host pass warns
@@ -7,18 +14,23 @@ that it does not know the feature, which is harmless).
 import os
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "qft_lib.hip")
-DEPS = [SRC] + [os.path.join(HERE, "csrc", f) for f in ("qft_device.hpp", "qft_schedule.hpp")]
+CSRC = os.path.join(HERE, "csrc")
+SRC = os.path.join(CSRC, "qft_lib.hip")
+TILES = os.path.join(CSRC, "qft_tiles.hip")
+DEPS = [SRC, TILES] + [os.path.join(CSRC, f) for f in
+                       ("qft_device.hpp", "qft_schedule.hpp", "qft_kernels.hpp")]
 LIB = os.path.join(HERE, "libqft.so")
 ROOT = os.path.dirname(HERE)
 HEADER = os.path.join(ROOT, "include", "qft.h")
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
+NOISE = "is not a recognized feature for this target"
 
 
 def hipcc():
@@ -30,16 +42,36 @@ def hipcc():
 
 def build(verbose=False):
     """Compile libqft.so (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + [SRC, "-o", tmp]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    noise = "is not a recognized feature for this target"
-    msgs = [l for l in (res.stdout + res.stderr).splitlines() if noise not in l]
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
+    cc = hipcc()
+    with tempfile.TemporaryDirectory(prefix="qft_build_") as tmp:
+        units = [(TILES, ["-DQFT_TILE_DT=%d" % dt, "-DQFT_TILE_TL=%d" % tl,
+                          "-DQFT_TILE_SWAP=%d" % sw], "tiles_%d_%d_%d.o" % (dt, tl, sw))
+                 for tl in (14, 13, 12) for dt in (0, 1) for sw in (0, 1)]
+        units.insert(0, (SRC, [], "lib.o"))
+        # at most one compiler per CPU (each takes ~1-2 GB)
+        jobs = max(1, min(len(units), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+        msgs, failed, running, pending = [], False, [], list(units)
+        while pending or running:
+            while pending and len(running) < jobs:
+                src, defs, obj = pending.pop(0)
+                cmd = [cc] + HIPCC_FLAGS + defs + ["-c", src, "-o", os.path.join(tmp, obj)]
+                running.append(subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                                stderr=subprocess.STDOUT, text=True))
+            pr = running.pop(0)
+            out, _ = pr.communicate()
+            msgs += [l for l in out.splitlines() if NOISE not in l]
+            failed |= pr.returncode != 0
+        if failed:
+            raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
+        out_tmp = LIB + ".tmp"
+        link = [cc, "--offload-arch=gfx950", "-shared", "-fPIC"] + \
+            [os.path.join(tmp, u[2]) for u in units] + ["-o", out_tmp]
+        res = subprocess.run(link, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("link failed:\n" + res.stdout + res.stderr)
     if verbose and msgs:
         print("\n".join(msgs), file=sys.stderr)
-    os.replace(tmp, LIB)
+    os.replace(out_tmp, LIB)
     return LIB
 
 

@@ -1156,13 +1156,13 @@ QFT_HD void bwd_chunk_s(WP W, int tid, Sync sync) {
   sync();
 }
 
-// Rounds per LDS pass (KC) and fused innermost rounds (KT).
-#ifndef QFT_KC
-#define QFT_KC 3
-#endif
-#ifndef QFT_KT
-#define QFT_KT 3
-#endif
+// Rounds per LDS pass (KC) of the forward and backward chunks, and fused
+// innermost rounds (KT) of the tail: KT = 4 where it saves a pass, i.e. when
+// the rounds above the tail, TOP - 4, are a multiple of KC.
+constexpr int QFT_KC = 3;
+QFT_HD constexpr int sweep_tail_rounds(int top) {
+  return top < 4 ? top : ((top - 4) % QFT_KC == 0 ? 4 : 3);
+}
 
 // forward chunks for rounds (KT, HI], top down
 template <int HI, int KT, int LGS, int NS, int NT, int MODE, bool SKIP0, class Sync, typename WP>
@@ -1189,7 +1189,7 @@ QFT_HD void bwd_rounds_s(WP W, int tid, Sync sync) {
 template <int TOP, int LGS, int NS, int NT, int MODE, bool SKIP0, class Sync, typename WP>
 QFT_HD void sweeps_s(WP W, const float* sec, int tid, Sync sync) {
   if constexpr (TOP >= 1) {
-    constexpr int KT = cmin<QFT_KT, TOP>::v;
+    constexpr int KT = sweep_tail_rounds(TOP);
     fwd_rounds_s<TOP, KT, LGS, NS, NT, MODE, SKIP0>(W, sec, tid, sync);
     tail_chunk_s<KT, LGS, NS, NT, MODE, SKIP0>(W, sec, tid);
     sync();
@@ -1246,11 +1246,445 @@ QFT_HD void chain_s(WP W, int tid, Sync sync, WSync wsync) {
   chain_levels_s<PW + 1, LOGN, LOGN, T, NT>(W, tid, sync);
 }
 
+// ===========================================================================
+// Fused DCT-0 / DST-0 chain (the backward half of ``dct``/``dst``, eqs.
+// qft_5C, qft_5D, qft_6), several levels per LDS round trip.
+//
+// Level Q = 2^q of the DCT chain takes E(i) = D_{Q/2}(i), i in [0, Q/4]
+// (cell i; E(Q/4) in the top cell) and the DCT-II block O(i), i < Q/4 (cell
+// Q/4 + i) to D_Q(i) = E(i) + O(i), D_Q(Q/2 - i) = E(i) - O(i) (i < Q/4) and
+// D_Q(Q/4) = E(Q/4); D_Q(i) goes to cell i, D_Q(Q/2) to the top cell.  Level
+// Q of the DST chain takes E(i) = S_{Q/2}(i), i in [1, Q/4) (cell i) and the
+// DST-II block O(i), i in [1, Q/4] (cell Q/4 + i - 1) to S_Q(i) = E(i) + O(i),
+// S_Q(Q/2 - i) = O(i) - E(i) and S_Q(Q/4) = O(Q/4), S_Q(i) to cell i.
+//
+// An index i of level Q feeds the outputs i and Q/2 - i.  Followed from one
+// input index k through K levels P, 2P, .., 2^(K-1) P, it gives 2^K outputs.
+// For 1 <= k < P/4 the index stays below Q/4 at every level Q, and output m
+// has index c_m + s_m k with compile-time c_m and s_m = +-1, the same on the
+// DCT and the DST side ("generic group" k).  Group 0 takes what is left: on
+// the DCT side index 0 together with the top cell (an index equal to Q/4
+// passes level Q unchanged, index 0 produces the next top Q/2), 2^K + 1
+// outputs; on the DST side the indices Q/4 that each level adds from O(Q/4),
+// 2^K - 1 outputs.  A pass over K levels is therefore P/4 independent groups
+// per side, each loading and storing its cells once.
+// ===========================================================================
+
+// Index constant and sign of output m of a generic group after a levels
+// (bit a-1-l of m selects the second output Q/2 - i of level l).
+QFT_HD constexpr int chain_c(int P, int a, int m) {
+  int c = 0;
+  for (int l = 0; l < a; ++l)
+    if ((m >> (a - 1 - l)) & 1) c = ((P << l) >> 1) - c;
+  return c;
+}
+QFT_HD constexpr int chain_sgn(int a, int m) {
+  int s = 1;
+  for (int l = 0; l < a; ++l)
+    if ((m >> (a - 1 - l)) & 1) s = -s;
+  return s;
+}
+
+// Index list of group 0 after a levels starting at P (DCT: index 0 and the
+// top index P/4 to begin with; DST: empty, one index added per level).
+struct ChainList {
+  int n;
+  int idx[40];
+};
+
+QFT_HD constexpr ChainList chain_special(int P, int a, bool dst) {
+  ChainList L{};
+  if (!dst) {
+    L.n = 2;
+    L.idx[0] = 0;
+    L.idx[1] = P / 4;
+  }
+  for (int l = 0; l < a; ++l) {
+    const int Q = P << l;
+    ChainList N{};
+    for (int m = 0; m < L.n; ++m) {
+      const int i = L.idx[m];
+      if (dst || i < Q / 4) {
+        N.idx[N.n++] = i;
+        N.idx[N.n++] = Q / 2 - i;
+      } else {
+        N.idx[N.n++] = i;
+      }
+    }
+    if (dst) N.idx[N.n++] = Q / 4;
+    L = N;
+  }
+  return L;
+}
+
+// For output m of the DCT group 0 after K levels: the DST group-0 output with
+// the same index, or -1 (indices 0 and Q/2, which have no DST partner).
+struct ChainPairing {
+  int ms[40];
+};
+
+QFT_HD constexpr ChainPairing chain_pairing(int P, int K) {
+  ChainPairing r{};
+  const ChainList d = chain_special(P, K, false);
+  const ChainList s = chain_special(P, K, true);
+  for (int m = 0; m < d.n; ++m) {
+    r.ms[m] = -1;
+    for (int q = 0; q < s.n; ++q)
+      if (s.idx[q] == d.idx[m]) r.ms[m] = q;
+  }
+  return r;
+}
+
+// Generic group k (1 <= k < P/4): loads E(k) and the 2^K - 1 block values it
+// meets, returns the 2^K outputs in v (output m has index c_m + s_m k).
+template <int P, int K, bool DST, typename SP>
+QFT_HD void chain_generic(SP sd, int k, float2* v) {
+  float2 o[1 << K];
+#pragma unroll
+  for (int l = 0; l < K; ++l) {
+    const int Q4 = (P << l) >> 2;
+#pragma unroll
+    for (int m = 0; m < (1 << l); ++m)
+      o[(1 << l) - 1 + m] = sd[Q4 + chain_c(P, l, m) + chain_sgn(l, m) * k - (DST ? 1 : 0)];
+  }
+  v[0] = sd[k];
+#pragma unroll
+  for (int l = 0; l < K; ++l) {
+#pragma unroll
+    for (int m = (1 << l) - 1; m >= 0; --m) {
+      const float2 E = v[m], O = o[(1 << l) - 1 + m];
+      v[2 * m] = cadd(E, O);
+      v[2 * m + 1] = DST ? csub(O, E) : csub(E, O);
+    }
+  }
+}
+
+template <int P, int K, typename SP>
+QFT_HD void chain_generic_store(SP sd, int k, const float2* v) {
+#pragma unroll
+  for (int m = 0; m < (1 << K); ++m) sd[chain_c(P, K, m) + chain_sgn(K, m) * k] = v[m];
+}
+
+// Group 0 of one side, levels L .. K-1 of the pass (v holds the list of
+// level L in the order of chain_special).
+template <int P, int K, int L, bool DST, typename SP>
+QFT_HD void chain_special_levels(SP sd, float2* v) {
+  if constexpr (L < K) {
+    constexpr ChainList cur = chain_special(P, L, DST);
+    constexpr ChainList nxt = chain_special(P, L + 1, DST);
+    constexpr int Q = P << L;
+    float2 nv[(1 << K) + 1];
+    int pos = 0;
+#pragma unroll
+    for (int m = 0; m < cur.n; ++m) {
+      const int i = cur.idx[m];
+      if (DST || i < Q / 4) {
+        const float2 E = v[m], O = sd[Q / 4 + i - (DST ? 1 : 0)];
+        nv[pos] = cadd(E, O);
+        nv[pos + 1] = DST ? csub(O, E) : csub(E, O);
+        pos += 2;
+      } else {
+        nv[pos] = v[m];
+        pos += 1;
+      }
+    }
+    if constexpr (DST) nv[nxt.n - 1] = sd[Q / 2 - 1];  // S_Q(Q/4) = O(Q/4)
+#pragma unroll
+    for (int m = 0; m < nxt.n; ++m) v[m] = nv[m];
+    chain_special_levels<P, K, L + 1, DST>(sd, v);
+  }
+}
+
+template <int P, int K, bool DST, typename SP>
+QFT_HD void chain_special_load(SP sd, SP top, float2* v) {
+  if constexpr (!DST) {
+    v[0] = sd[0];
+    v[1] = *top;
+  }
+  chain_special_levels<P, K, 0, DST>(sd, v);
+}
+
+template <int P, int K, bool DST, typename SP>
+QFT_HD void chain_special_store(SP sd, SP top, const float2* v) {
+  constexpr ChainList fin = chain_special(P, K, DST);
+  constexpr int half = (P << (K - 1)) >> 1;  // Q/2 of the last level
+#pragma unroll
+  for (int m = 0; m < fin.n; ++m) {
+    const int i = fin.idx[m];
+    if (!DST && i == half) *top = v[m];
+    else sd[i] = v[m];
+  }
+}
+
+// Side pointers of transform t: DCT side, DST side, top cell.
+template <typename WP>
+struct TileSides {
+  WP W;
+  int logn;
+  QFT_HD WP dc(int t) const { return W + (t << logn); }
+  QFT_HD WP ds(int t) const { return W + (t << logn) + (1 << (logn - 1)); }
+  QFT_HD WP top(int t) const { return ds(t); }
+};
+
+// One pass: levels P .. 2^(K-1) P of both sides of transforms [0, T); item =
+// (transform, group) with the DCT and the DST group of the same index, over
+// NT threads.  All loads, then `sync`, then all stores, then `sync`.
+template <int P, int K, int T, int NT, class Sync, class Acc>
+QFT_HD void chain_pass(const Acc& acc, int tid, bool active, Sync sync) {
+  constexpr int G = P / 4;
+  constexpr int total = T * G;
+  constexpr int NI = (total + NT - 1) / NT;
+  constexpr int S = (1 << K) + 1;
+  float2 vc[NI][S], vs[NI][S];
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int i = tid + it * NT;
+    if (active && i < total) {
+      const int t = i / G, g = i - t * G;
+      if (g == 0) {
+        chain_special_load<P, K, false>(acc.dc(t), acc.top(t), vc[it]);
+        chain_special_load<P, K, true>(acc.ds(t), acc.top(t), vs[it]);
+      } else {
+        chain_generic<P, K, false>(acc.dc(t), g, vc[it]);
+        chain_generic<P, K, true>(acc.ds(t), g, vs[it]);
+      }
+    }
+  }
+  sync();
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int i = tid + it * NT;
+    if (active && i < total) {
+      const int t = i / G, g = i - t * G;
+      if (g == 0) {
+        chain_special_store<P, K, false>(acc.dc(t), acc.top(t), vc[it]);
+        chain_special_store<P, K, true>(acc.ds(t), acc.top(t), vs[it]);
+      } else {
+        chain_generic_store<P, K>(acc.dc(t), g, vc[it]);
+        chain_generic_store<P, K>(acc.ds(t), g, vs[it]);
+      }
+    }
+  }
+  sync();
+}
+
+// Levels 1 .. B of one side in one thread (B >= 1; DCT base P = 2 is
+// (c(0) + c(N/2), c(0) - c(N/2)), DST base P = 4 is the identity).
+template <int B, typename SP>
+QFT_HD void chain_base_dct(SP sd, SP top) {
+  constexpr int NV = (1 << (B - 1)) + 1;
+  float2 D[NV], in[NV];
+#pragma unroll
+  for (int c = 0; c < NV - 1; ++c) in[c] = sd[c];
+  const float2 ct = *top;
+  D[0] = cadd(in[0], ct);
+  D[1] = csub(in[0], ct);
+#pragma unroll
+  for (int q = 2; q <= B; ++q) {
+    const int Q = 1 << q;
+    float2 nd[NV];
+#pragma unroll
+    for (int i = 0; i < Q / 4; ++i) {
+      const float2 O = in[Q / 4 + i];
+      nd[i] = cadd(D[i], O);
+      nd[Q / 2 - i] = csub(D[i], O);
+    }
+    nd[Q / 4] = D[Q / 4];
+#pragma unroll
+    for (int i = 0; i <= Q / 2; ++i) D[i] = nd[i];
+  }
+#pragma unroll
+  for (int c = 0; c < NV - 1; ++c) sd[c] = D[c];
+  *top = D[NV - 1];
+}
+
+template <int B, typename SP>
+QFT_HD void chain_base_dst(SP sd) {
+  if constexpr (B >= 3) {
+    constexpr int NV = 1 << (B - 1);
+    float2 Sv[NV], in[NV];
+#pragma unroll
+    for (int c = 1; c < NV; ++c) in[c] = sd[c];
+    Sv[1] = in[1];
+#pragma unroll
+    for (int q = 3; q <= B; ++q) {
+      const int Q = 1 << q;
+      float2 ns[NV];
+#pragma unroll
+      for (int i = 1; i < Q / 4; ++i) {
+        const float2 O = in[Q / 4 + i - 1];
+        ns[i] = cadd(Sv[i], O);
+        ns[Q / 2 - i] = csub(O, Sv[i]);
+      }
+      ns[Q / 4] = in[Q / 2 - 1];
+#pragma unroll
+      for (int i = 1; i < Q / 2; ++i) Sv[i] = ns[i];
+    }
+#pragma unroll
+    for (int c = 1; c < NV; ++c) sd[c] = Sv[c];
+  }
+}
+
+// Global input/output of the transforms of a tile.  SWAP loads and stores
+// every value with its real and imaginary parts exchanged, which turns the
+// forward transform into the adjoint: F^H g = swap(F swap(g)).  Transform t
+// of the tile starts at element x + base + t 2^LOGN (ContigIO, a contiguous
+// batch) or at x + offs[t] (GatherIO, an uneven batch's offset list).
+template <int DT, bool SWAP>
+struct SwapIO {
+  using E = typename Store<DT>::T;
+  QFT_HD static float2 load(const E* p, int i) { return sw<SWAP>(Store<DT>::ld(p, i)); }
+  QFT_HD static void store(E* p, int i, float2 v) { Store<DT>::st(p, i, sw<SWAP>(v)); }
+};
+
+template <int DT, bool SWAP, int LOGN>
+struct ContigIO : SwapIO<DT, SWAP> {
+  using E = typename Store<DT>::T;
+  const E* x;
+  E* X;
+  QFT_HD ContigIO(const E* x_, E* X_) : x(x_), X(X_) {}
+  QFT_HD const E* src(int t) const { return x + ((int64_t)t << LOGN); }
+  QFT_HD E* dst(int t) const { return X + ((int64_t)t << LOGN); }
+};
+
+template <int DT, bool SWAP>
+struct GatherIO : SwapIO<DT, SWAP> {
+  using E = typename Store<DT>::T;
+  const E* x;
+  E* X;
+  const int64_t* offs;
+  QFT_HD GatherIO(const E* x_, E* X_, const int64_t* o) : x(x_), X(X_), offs(o) {}
+  QFT_HD const E* src(int t) const { return x + offs[t]; }
+  QFT_HD E* dst(int t) const { return X + offs[t]; }
+};
+
+struct NoIO {};
+
+// Transforms [t0, t0 + T') of an accessor, as an accessor of their own.
+template <class Acc>
+struct ChainSub {
+  Acc a;
+  int t0;
+  QFT_HD auto dc(int t) const { return a.dc(t0 + t); }
+  QFT_HD auto ds(int t) const { return a.ds(t0 + t); }
+  QFT_HD auto top(int t) const { return a.top(t0 + t); }
+};
+
+// Levels 1 .. B of the base: one thread per (transform, side).
+template <int B, int T, int NT, class Acc>
+QFT_HD void chain_base(const Acc& acc, int tid, bool active) {
+  constexpr int total = 2 * T;
+#pragma unroll
+  for (int it = 0; it < (total + NT - 1) / NT; ++it) {
+    const int i = tid + it * NT;
+    if (active && i < total) {
+      const int t = i >> 1;
+      if (i & 1) chain_base_dst<B>(acc.ds(t));
+      else chain_base_dct<B>(acc.dc(t), acc.top(t));
+    }
+  }
+}
+
+// Passes of three levels starting at level PL while PL < PEND, over T
+// transforms and NT threads ordered by `sync`.
+template <int PL, int PEND, int T, int NT, class Sync, class Acc>
+QFT_HD void chain_passes(const Acc& acc, int tid, bool active, Sync sync) {
+  if constexpr (PL < PEND) {
+    chain_pass<(1 << PL), 3, T, NT>(acc, tid, active, sync);
+    chain_passes<PL + 3, PEND, T, NT>(acc, tid, active, sync);
+  }
+}
+
+// First pass level (>= PL, in steps of 3, below PEND) whose items per wave
+// exceed the wave's lanes.
+QFT_HD constexpr int chain_first_block_pass(int pl, int pend, int tpw, int lanes) {
+  return (pl >= pend || tpw * ((1 << pl) / 4) > lanes)
+             ? pl
+             : chain_first_block_pass(pl + 3, pend, tpw, lanes);
+}
+
+template <class IO, typename EP>
+QFT_HD void combine_put(const IO& io, EP Xt, int n, int k, float2 C, float2 S) {
+  io.store(Xt, k, make_float2(C.x + S.y, C.y - S.x));
+  io.store(Xt, n - k, make_float2(C.x - S.y, C.y + S.x));
+}
+
+// Last pass (levels PLOG-2 .. PLOG) fused with the cdft combine of Sec. 4.1:
+// the DCT and the DST group of one index hold C and S at the same indices.
+template <int PLOG, int T, int NT, class Acc, class IO>
+QFT_HD void chain_top_combine(const Acc& acc, const IO& io, int Tact, int tid) {
+  constexpr int N = 1 << PLOG, P = N / 4, G = P / 4, K = 3;
+  constexpr int total = T * G;
+  constexpr int S = (1 << K) + 1;
+#pragma unroll
+  for (int it = 0; it < (total + NT - 1) / NT; ++it) {
+    const int i = tid + it * NT;
+    if (i < total) {
+      const int t = i / G, g = i - t * G;
+      if (t < Tact) {
+        const auto Xt = io.dst(t);
+        float2 vc[S], vs[S];
+        if (g == 0) {
+          chain_special_load<P, K, false>(acc.dc(t), acc.top(t), vc);
+          chain_special_load<P, K, true>(acc.ds(t), acc.top(t), vs);
+          constexpr ChainList fin = chain_special(P, K, false);
+          constexpr ChainPairing pr = chain_pairing(P, K);
+#pragma unroll
+          for (int m = 0; m < fin.n; ++m) {
+            if (pr.ms[m] < 0) io.store(Xt, fin.idx[m], vc[m]);  // X(0), X(N/2)
+            else combine_put(io, Xt, N, fin.idx[m], vc[m], vs[pr.ms[m]]);
+          }
+        } else {
+          chain_generic<P, K, false>(acc.dc(t), g, vc);
+          chain_generic<P, K, true>(acc.ds(t), g, vs);
+#pragma unroll
+          for (int m = 0; m < (1 << K); ++m)
+            combine_put(io, Xt, N, chain_c(P, K, m) + chain_sgn(K, m) * g, vc[m], vs[m]);
+        }
+      }
+    }
+  }
+}
+
+// Base levels of a chain of PLOG levels: the rest is a whole number of
+// three-level passes, the last one starting at PLOG - 2.
+QFT_HD constexpr int chain_base_levels(int plog) {
+  return plog <= 4 ? plog : ((plog - 3) % 3 == 0 ? 3 : ((plog - 3) % 3 == 1 ? 4 : 2));
+}
+
+// Levels 1 .. PLOG of T transforms (PLOG >= 5): levels 1..B, then passes of
+// three levels.  The base and the passes with at most one item per lane run
+// per wavefront (wave w owns transforms [w TPW, (w+1) TPW), ordered by
+// `wsync`); the others use the whole workgroup.  COMBINE: the last pass
+// writes X(k), X(N-k) for t < Tact to X instead of the side cells and ends
+// without a barrier (the caller synchronises before it reuses the LDS).
+template <int PLOG, int T, int NT, int WAVE, bool COMBINE, class Sync, class WSync, class Acc,
+          class IO>
+QFT_HD void chain_fused(const Acc& acc, const IO& io, int Tact, int tid, Sync sync, WSync wsync) {
+  static_assert(PLOG >= 5, "the fused chain starts at N = 32");
+  constexpr int B = chain_base_levels(PLOG);
+  constexpr int LANES = NT < WAVE ? NT : WAVE;
+  constexpr int NW = NT / LANES;
+  constexpr int TPW = (T + NW - 1) / NW;
+  constexpr int PTOP = PLOG - 2;
+  constexpr int PBLK = chain_first_block_pass(B + 1, PTOP, TPW, LANES);
+  static_assert(2 * TPW <= LANES, "base items exceed one wavefront");
+  const int w = tid / LANES, lane = tid - w * LANES;
+  const bool wact = w * TPW < T;
+  const ChainSub<Acc> sub{acc, w * TPW};
+  chain_base<B, TPW, LANES>(sub, lane, wact);
+  wsync();
+  chain_passes<B + 1, PBLK, TPW, LANES>(sub, lane, wact, wsync);
+  sync();
+  chain_passes<PBLK, PTOP, T, NT>(acc, tid, true, sync);
+  if constexpr (COMBINE) chain_top_combine<PLOG, T, NT>(acc, io, Tact, tid);
+  else chain_pass<(1 << PTOP), 3, T, NT>(acc, tid, true, sync);
+}
+
 // Whole tile: T transforms of 2^LOGN points, NT threads (LOGN >= 1).
-template <int DT, bool SWAP, int LOGN, int T, int NT, int WAVE, class Sync, class WSync,
-          typename WP>
-QFT_HD void tile_body_s(const typename Store<DT>::T* x, typename Store<DT>::T* X, WP W, int Tact,
-                        const float* sec, int tid, Sync sync, WSync wsync) {
+template <int LOGN, int T, int NT, int WAVE, class Sync, class WSync, typename WP, class IO>
+QFT_HD void tile_body_s(const IO& io, WP W, int Tact, const float* sec, int tid, Sync sync,
+                        WSync wsync) {
   constexpr int n = 1 << LOGN, h = n >> 1;
   constexpr int total = T << (LOGN - 1);
   constexpr int FI = (total + NT - 1) / NT;
@@ -1262,9 +1696,9 @@ QFT_HD void tile_body_s(const typename Store<DT>::T* x, typename Store<DT>::T* X
     if (i < tot_act) {
       const int t = i >> (LOGN - 1);
       const int m = i & (h - 1);
-      const typename Store<DT>::T* xt = x + ((int64_t)t << LOGN);
-      av[it] = Store<DT>::ld(xt, m);
-      bv[it] = Store<DT>::ld(xt, m == 0 ? h : n - m);
+      const auto xt = io.src(t);
+      av[it] = io.load(xt, m);
+      bv[it] = io.load(xt, m == 0 ? h : n - m);
     }
   }
 #pragma unroll
@@ -1274,7 +1708,7 @@ QFT_HD void tile_body_s(const typename Store<DT>::T* x, typename Store<DT>::T* X
       const int t = i >> (LOGN - 1);
       const int m = i & (h - 1);
       auto w = W + (t << LOGN);
-      const float2 a = sw<SWAP>(av[it]), b = sw<SWAP>(bv[it]);
+      const float2 a = av[it], b = bv[it];
       if (m == 0) {
         w[0] = a;
         w[h] = b;
@@ -1289,6 +1723,10 @@ QFT_HD void tile_body_s(const typename Store<DT>::T* x, typename Store<DT>::T* X
   sync();
   if constexpr (LOGN >= 3)
     sweeps_s<LOGN - 2, LOGN - 1, 2 * T, NT, SIDES_ALT, true>(W, sec, tid, sync);
+  if constexpr (LOGN >= 5) {
+    chain_fused<LOGN, T, NT, WAVE, true>(TileSides<WP>{W, LOGN}, io, Tact, tid, sync, wsync);
+    return;
+  }
   chain_s<LOGN, T, NT, WAVE>(W, tid, sync, wsync);
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
@@ -1296,15 +1734,13 @@ QFT_HD void tile_body_s(const typename Store<DT>::T* x, typename Store<DT>::T* X
     if (i < tot_act) {
       const int t = i >> (LOGN - 1);
       const int k = i & (h - 1);
-      typename Store<DT>::T* Xt = X + ((int64_t)t << LOGN);
+      const auto Xt = io.dst(t);
       auto w = W + (t << LOGN);
       if (k == 0) {
-        Store<DT>::st(Xt, 0, sw<SWAP>(w[0]));
-        Store<DT>::st(Xt, h, sw<SWAP>(w[h]));
+        io.store(Xt, 0, w[0]);
+        io.store(Xt, h, w[h]);
       } else {
-        const float2 C = w[k], S = w[h + k];
-        Store<DT>::st(Xt, k, sw<SWAP>(make_float2(C.x + S.y, C.y - S.x)));
-        Store<DT>::st(Xt, n - k, sw<SWAP>(make_float2(C.x - S.y, C.y + S.x)));
+        combine_put(io, Xt, n, k, w[k], w[h + k]);
       }
     }
   }
@@ -1375,80 +1811,6 @@ QFT_HD float2 heap_fold_value(const typename Store<DT>::T* xt, int logn, int p) 
   return DST ? csub(a, b) : cadd(a, b);
 }
 
-// Pass A for one workgroup: w = side * 4 + segment.
-template <int DT, bool SWAP, int MC_LOG2, int NT, class Sync, class WSync, typename GP,
-          typename LP>
-QFT_HD void tp_pass_a(const typename Store<DT>::T* xt, GP wt, LP L, int w, const float* sec,
-                      int tid, int wave_size, Sync sync, WSync wsync) {
-  constexpr int MC = 1 << MC_LOG2;
-  constexpr int logn = MC_LOG2 + 3;
-  constexpr int N = 1 << logn, h = N >> 1;
-  constexpr int NI = MC / NT;  // cells per thread
-  constexpr int nthr = NT;
-  const int side = w >> 2, j = w & 3;
-  const bool dst = side != 0;
-  // ---- gather ----
-  float2 v[NI];
-#pragma unroll
-  for (int it = 0; it < NI; ++it) {
-    const int q = tid + it * nthr;
-    if (q >= MC) continue;
-    const int p = j * MC + q;
-    if (j < 2) {
-      if (p == 0) {
-        v[it] = make_float2(0.f, 0.f);
-        if (!dst) v[it] = sw<SWAP>(Store<DT>::ld(xt, 0));  // c(0)
-      } else {
-        v[it] = dst ? heap_fold_value<DT, SWAP, true>(xt, logn, p)
-                    : heap_fold_value<DT, SWAP, false>(xt, logn, p);
-      }
-    } else {
-      // block N/4 (cells [2MC, 4MC)), top round S = 2MC: pair (q, 2MC-1-q),
-      // odd n = 2q+1 and its mirror N/2 - n
-      const int n = 2 * q + 1;
-      const float2 a0 = sw<SWAP>(Store<DT>::ld(xt, n));
-      const float2 b0 = sw<SWAP>(Store<DT>::ld(xt, N - n));
-      const float2 a1 = sw<SWAP>(Store<DT>::ld(xt, h - n));
-      const float2 b1 = sw<SWAP>(Store<DT>::ld(xt, h + n));
-      const float2 y0 = dst ? csub(a0, b0) : cadd(a0, b0);  // fold at n
-      const float2 y1 = dst ? csub(a1, b1) : cadd(a1, b1);  // fold at N/2 - n
-      const float2 sum = cadd(y0, y1), dif = csub(y0, y1);
-      if (j == 2) v[it] = dst ? dif : sum;
-      else v[it] = cscale(dst ? sum : dif, sec[MC + q]);
-    }
-  }
-  float2 topv = make_float2(0.f, 0.f);
-  if (!dst && j == 0 && tid == 0) topv = sw<SWAP>(Store<DT>::ld(xt, h));  // c(N/2)
-#pragma unroll
-  for (int it = 0; it < NI; ++it) {
-    const int q = tid + it * nthr;
-    if (q < MC) L[q] = v[it];
-  }
-  if (!dst && j == 0 && tid == 0) L[MC] = topv;
-  sync();
-  // ---- remaining rounds (and the chain for the heads) ----
-  if (j == 0) {
-    if (dst) {
-      sweeps_s<MC_LOG2 - 1, MC_LOG2, 1, NT, SIDES_DST, true>(L, sec, tid, sync);
-      chain_one_side<true>(L, L + MC, MC_LOG2 + 1, tid, nthr, wave_size, sync, wsync);
-    } else {
-      sweeps_s<MC_LOG2 - 1, MC_LOG2, 1, NT, SIDES_DCT, true>(L, sec, tid, sync);
-      chain_one_side<false>(L, L + MC, MC_LOG2 + 1, tid, nthr, wave_size, sync, wsync);
-    }
-  } else {
-    if (dst) sweeps_s<MC_LOG2, MC_LOG2, 1, NT, SIDES_DST, false>(L, sec, tid, sync);
-    else sweeps_s<MC_LOG2, MC_LOG2, 1, NT, SIDES_DCT, false>(L, sec, tid, sync);
-  }
-  // ---- write the segment to the heap buffer ----
-  auto seg = wt + (side * h + j * MC);
-#pragma unroll
-  for (int it = 0; it < NI; ++it) {
-    const int q = tid + it * nthr;
-    if (q < MC && !(dst && j == 0 && q == 0)) seg[q] = (float2)L[q];
-  }
-  if (!dst && j == 0 && tid == 0) wt[h] = (float2)L[MC];  // D_{2MC}(MC): top cell
-}
-
 // Pass B, thread k of a transform (0 <= k < N/8).  Heap contents after pass A
 // (DCT side; the DST side is alike with its own index conventions):
 //   cells [0, MC) + top : D_{N/4} (chain output of the head)
@@ -1513,20 +1875,23 @@ QFT_HD void tp_pass_b(GP wt, typename Store<DT>::T* Xt, int k) {
   }
 }
 
-// Pass-A workgroups per transform and pass-B threads per transform.
-QFT_HD constexpr int tp_blocks_a() { return 8; }
-
-
-
-
 // Pass A with both sides of one segment index j in the same workgroup: the
 // DCT and DST cells of a position come from the same x samples (c = a + b,
 // d = a - b), so x is gathered once for both.  LDS: DCT segment at L[0, MC),
 // DST segment at L[MC, 2MC), the DCT top cell (c(N/2) / D(MC)) at L[2MC].
-template <int DT, bool SWAP, int MC_LOG2, int NT, class Sync, class WSync, typename GP,
-          typename LP>
+template <typename LP>
+struct HeadSides {  // the head segments of pass A: DCT, DST and the top cell
+  LP L;
+  int mc;
+  QFT_HD LP dc(int) const { return L; }
+  QFT_HD LP ds(int) const { return L + mc; }
+  QFT_HD LP top(int) const { return L + 2 * mc; }
+};
+
+template <int DT, bool SWAP, int MC_LOG2, int NT, int WAVE, class Sync, class WSync,
+          typename GP, typename LP>
 QFT_HD void tp_pass_a2(const typename Store<DT>::T* xt, GP wt, LP L, int j, const float* sec,
-                       int tid, int wave_size, Sync sync, WSync wsync) {
+                       int tid, Sync sync, WSync wsync) {
   constexpr int MC = 1 << MC_LOG2;
   constexpr int logn = MC_LOG2 + 3;
   constexpr int N = 1 << logn, h = N >> 1;
@@ -1579,8 +1944,13 @@ QFT_HD void tp_pass_a2(const typename Store<DT>::T* xt, GP wt, LP L, int j, cons
   sync();
   if (j == 0) {
     sweeps_s<MC_LOG2 - 1, MC_LOG2, 2, NT, SIDES_ALT, true>(L, sec, tid, sync);
-    chain_one_side<false>(L, L + 2 * MC, MC_LOG2 + 1, tid, NT, wave_size, sync, wsync);
-    chain_one_side<true>(L + MC, L + 2 * MC, MC_LOG2 + 1, tid, NT, wave_size, sync, wsync);
+    if constexpr (MC_LOG2 + 1 >= 5) {
+      chain_fused<MC_LOG2 + 1, 1, NT, WAVE, false>(HeadSides<LP>{L, MC}, NoIO{}, 1, tid, sync,
+                                                    wsync);
+    } else {
+      chain_one_side<false>(L, L + 2 * MC, MC_LOG2 + 1, tid, NT, WAVE, sync, wsync);
+      chain_one_side<true>(L + MC, L + 2 * MC, MC_LOG2 + 1, tid, NT, WAVE, sync, wsync);
+    }
   } else {
     sweeps_s<MC_LOG2, MC_LOG2, 2, NT, SIDES_ALT, false>(L, sec, tid, sync);
   }

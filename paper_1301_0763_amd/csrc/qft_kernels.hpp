@@ -1,0 +1,64 @@
+// Definitions shared by the library's translation units: the device barrier
+// functors and LDS layout constants of the kernels, and the launch interface
+// of the persistent tile kernels (built once per storage type in
+// qft_tiles.hip, called from the plan code in qft_lib.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qft_device.hpp"
+
+namespace qftk {
+
+struct DevSync {
+  __device__ __forceinline__ void operator()() const { __syncthreads(); }
+};
+
+// Orders the LDS accesses of one wavefront (its lanes exchange data through
+// LDS between chain levels without a workgroup barrier).
+struct DevWaveSync {
+  __device__ __forceinline__ void operator()() const {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+};
+
+constexpr int kWave = 64;
+constexpr int kPad = 3;  // LDS padding: one spare cell per 2^kPad cells
+
+// Persistent tile kernel with tiles of 2^tl cells (12 <= tl <= 14): 16 cells
+// per thread, and as many resident workgroups per CU as the LDS allows
+// (2^tl padded float2 cells out of 160 KiB).
+constexpr int kMinTileLog2 = 12;
+constexpr int kMaxTileLog2 = 14;
+constexpr int tile_threads(int tl) { return (1 << tl) / 16; }
+constexpr int tile_wgs_per_cu(int tl) { return tl <= 12 ? 4 : (tl == 13 ? 2 : 1); }
+
+// One tile-kernel launch.  Uniform groups (d_tiles == nullptr): a
+// contiguous batch of `ubatch` transforms of 2^ulog2n points in tiles of
+// T = 2^(tl - ulog2n) transforms (the last one ragged), one workgroup per
+// tile (tl = max(12, ulog2n)).  Uneven groups: tile w = (log2n, first,
+// count, 0) holds `count` transforms of 2^log2n points at element offsets
+// d_offs[first .. first + count); `grid` workgroups stride over the tiles
+// (grid = ntiles: one workgroup per tile) and exit after their last one.
+struct TileGroup {
+  int tl;
+  int ntiles;
+  int grid;
+  int4* d_tiles;
+  int64_t* d_offs;
+  int ulog2n;
+  int64_t ubatch;
+};
+
+// Launches one group with the tile kernels of storage type DT (0: complex
+// FP32, 1: complex FP16), tile size 2^TL and direction SWAP (adjoint).
+// Defined in qft_tiles.hip and explicitly instantiated there once per
+// (DT, TL, SWAP), each in a translation unit of its own.
+template <int DT, int TL, bool SWAP>
+hipError_t launch_tiles(const TileGroup& g, const void* in, void* out, const float* sec,
+                        hipStream_t st);
+
+}  // namespace qftk

@@ -1,19 +1,23 @@
-// Improved-QFT DFT library for gfx950: kernels, plans and the C ABI of
-// include/qft.h.  The cell layout and the formula of every step are in
-// qft_device.hpp.
+// Improved-QFT DFT library for gfx950: plans, schedules, the multi-pass and
+// two-pass kernels, and the C ABI of include/qft.h.  The cell layout and the
+// formula of every step are in qft_device.hpp; the persistent tile kernels
+// (N <= 2^14) are in qft_tiles.hip.
 //
 // Execution paths
-//  * tile kernel (N <= 2^14): one workgroup holds T = 2^TILE / N whole
-//    transforms in LDS and runs fold -> forward rounds -> backward rounds ->
-//    DCT-0/DST-0 chain -> combine, reading and writing HBM once.
-//  * persistent uneven kernel: the same per-tile work over a size-sorted work
-//    list of tiles (each tile = transforms of one size), grid = resident
-//    workgroups, static striding (every workgroup exits after its last tile).
-//  * multi-pass path (N > 2^14): fold into a global heap buffer, forward
+//  * persistent tile kernel (N <= 2^14): a workgroup holds whole transforms
+//    in LDS (tiles of 2^12, 2^13 or 2^14 cells) and runs fold -> forward
+//    rounds -> backward rounds -> fused DCT-0/DST-0 chain and combine,
+//    reading and writing HBM once; workgroups stride over a list of tiles.
+//  * two-pass path (N = 2^15, 2^16): pass A gathers each quarter of a
+//    transform's heap (both sides) from x and runs its rounds in LDS, pass B
+//    streams the top backward round, the last two chain levels and the
+//    combine.
+//  * multi-pass path (N > 2^16): fold into a global heap buffer, forward
 //    rounds of the blocks larger than one 2^12-cell segment in global
-//    memory, one LDS pass per segment (the core pass closes the small end of
-//    the chain), backward rounds and chain levels of the large blocks in
-//    global memory (ping-pong buffers for the backward rounds), combine.
+//    memory, one LDS pass per segment, backward rounds and chain levels of
+//    the large blocks in global memory, combine.
+// A plan holds one or more schedules (which transform sizes run in which
+// tile-size group); qft_plan_autotune times them and keeps the fastest.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,69 +25,14 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
-#include "qft_device.hpp"
+#include "qft_kernels.hpp"
 #include "qft_schedule.hpp"
 #include "../../include/qft.h"
 
 namespace qftk {
-
-struct DevSync {
-  __device__ __forceinline__ void operator()() const { __syncthreads(); }
-};
-
-// Orders the LDS accesses of one wavefront (its lanes exchange data through
-// LDS between chain levels without a workgroup barrier).
-struct DevWaveSync {
-  __device__ __forceinline__ void operator()() const {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-};
-
-constexpr int kWave = 64;
-#ifndef QFT_PAD
-#define QFT_PAD 3
-#endif
-constexpr int kPad = QFT_PAD;  // LDS padding: one spare cell per 2^kPad cells
-
-// Specialised tile kernel: T = 2^(TILE_LOG2 - LOGN) transforms of 2^LOGN.
-template <int LOGN, int TILE_LOG2, int BLOCK, int DT, bool SWAP>
-__global__ __launch_bounds__(BLOCK) void tile_kernel_s(const typename Store<DT>::T* x,
-                                                        typename Store<DT>::T* X, int64_t batch,
-                                                        const float* sec) {
-  constexpr int T = 1 << (TILE_LOG2 - LOGN);
-  __shared__ float2 Wl[padded_cells<kPad>(1 << TILE_LOG2)];
-  const PadPtr<kPad> W{Wl, 0};
-  const int64_t t0 = (int64_t)blockIdx.x * T;
-  const int Tact = (int)min((int64_t)T, batch - t0);
-  const int64_t off = t0 << LOGN;
-  tile_body_s<DT, SWAP, LOGN, T, BLOCK, kWave>(x + off, X + off, W, Tact, sec, (int)threadIdx.x,
-                                               DevSync{}, DevWaveSync{});
-}
-
-// Persistent kernel for uneven plans: tiles[w] = (logn, first, count, 0)
-// covers transforms with element offsets offs[first .. first+count).
-// Workgroups stride over the size-sorted list and exit after their last tile.
-template <int TILE_LOG2, int BLOCK, int DT, bool SWAP>
-__global__ __launch_bounds__(BLOCK) void uneven_kernel(const typename Store<DT>::T* x,
-                                                        typename Store<DT>::T* X,
-                                                        const int4* __restrict__ tiles,
-                                                        int ntiles,
-                                                        const int64_t* __restrict__ offs,
-                                                        const float* sec) {
-  __shared__ float2 Wl[padded_cells<kPad>(1 << TILE_LOG2)];
-  const PadPtr<kPad> W{Wl, 0};
-  constexpr int CPT = (1 << TILE_LOG2) / BLOCK;
-  for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
-    const int4 d = tiles[w];
-    tile_body<DT, SWAP, CPT>(x, X, W, d.x, d.z, offs + d.y, sec, (int)threadIdx.x, BLOCK, kWave,
-                             DevSync{}, DevWaveSync{});
-    __syncthreads();
-  }
-}
 
 constexpr int MP_BLOCK = 256;
 
@@ -136,27 +85,11 @@ __global__ __launch_bounds__(BLOCK) void mp_segment_kernel(float2* W, int logn,
                                 DevSync{}, DevWaveSync{});
 }
 
-// Two-pass path, N = 8 * 2^MC_LOG2.  Pass A: 8 workgroups per transform
-// (side x segment).  Block b serves transform 8*(b/64) + b%8 and workgroup
-// role (b/8)%8, so that the eight workgroups of a transform share b%8, i.e.
-// land on the same XCD (round-robin dispatch) and find x in that XCD's L2.
-template <int MC_LOG2, int BLOCK, int DT, bool SWAP>
-__global__ __launch_bounds__(BLOCK) void tp_a_kernel(const typename Store<DT>::T* x, float2* W,
-                                                      int64_t batch, const float* sec) {
-  constexpr int MC = 1 << MC_LOG2;
-  constexpr int logn = MC_LOG2 + 3;
-  __shared__ float2 Ll[padded_cells<kPad>(MC + 1)];
-  const PadPtr<kPad> L{Ll, 0};
-  const int64_t b = blockIdx.x;
-  const int r = (int)(b & 63);
-  const int64_t t = (b >> 6) * 8 + (r & 7);
-  if (t >= batch) return;
-  tp_pass_a<DT, SWAP, MC_LOG2, BLOCK>(x + (t << logn), W + (t << logn), L, r >> 3, sec,
-                                      (int)threadIdx.x, kWave, DevSync{}, DevWaveSync{});
-}
-
-// Pass A with both sides per workgroup: 4 workgroups per transform, block b
-// serves transform 8*(b/32) + b%8 and segment (b/8)%4 (same XCD per transform).
+// Two-pass path, N = 8 * 2^MC_LOG2.  Pass A: both sides of one segment per
+// workgroup, 4 workgroups per transform; block b serves transform
+// 8*(b/32) + b%8 and segment (b/8)%4, so that the workgroups of a transform
+// share b%8, i.e. land on the same XCD (round-robin dispatch) and find x in
+// that XCD's L2.
 template <int MC_LOG2, int BLOCK, int DT, bool SWAP>
 __global__ __launch_bounds__(BLOCK) void tp_a2_kernel(const typename Store<DT>::T* x, float2* W,
                                                        int64_t batch, const float* sec) {
@@ -168,8 +101,8 @@ __global__ __launch_bounds__(BLOCK) void tp_a2_kernel(const typename Store<DT>::
   const int r = (int)(b & 31);
   const int64_t t = (b >> 5) * 8 + (r & 7);
   if (t >= batch) return;
-  tp_pass_a2<DT, SWAP, MC_LOG2, BLOCK>(x + (t << logn), W + (t << logn), L, r >> 3, sec,
-                                       (int)threadIdx.x, kWave, DevSync{}, DevWaveSync{});
+  tp_pass_a2<DT, SWAP, MC_LOG2, BLOCK, kWave>(x + (t << logn), W + (t << logn), L, r >> 3, sec,
+                                              (int)threadIdx.x, DevSync{}, DevWaveSync{});
 }
 
 template <int MC_LOG2, int DT, bool SWAP>
@@ -194,14 +127,20 @@ namespace {
 
 thread_local int g_last_hip_error = 0;
 
-constexpr int kMaxTileLog2 = 14;  // single-workgroup transforms
-constexpr int kSegLog2 = 12;      // multi-pass segment size
-constexpr int kUnevenTileLog2 = 14;
-constexpr int kUnevenBlock = 1024;
+constexpr int kSegLog2 = 12;  // multi-pass segment size
 
+// Transforms handled outside the tile groups (N > 2^14): `batch` contiguous
+// transforms of 2^log2n points starting at element `offset`.
 struct LargeItem {
   int log2n;
-  int64_t offset;  // element offset
+  int64_t offset;
+  int64_t batch;
+};
+
+// A schedule: tile-group launches, in order, for the transforms of N <= 2^14.
+struct Schedule {
+  std::string name;
+  std::vector<qftk::TileGroup> groups;
 };
 
 }  // namespace
@@ -216,15 +155,14 @@ struct qft_plan_s {
   double flops_5nlogn = 0.0;
   double flops_actual = 0.0;
   int max_log2n = 0;
+  int cus = 0;
   float* d_sec = nullptr;
-  float2* d_work = nullptr;  // 2 buffers for the multi-pass path
+  float2* d_work = nullptr;  // 2 buffers for the two-pass / multi-pass paths
   int64_t work_cells = 0;    // cells per buffer
-  // uneven
-  int4* d_tiles = nullptr;
-  int ntiles = 0;
-  int64_t* d_offs = nullptr;
-  int persistent_grid = 0;
-  std::vector<LargeItem> large;
+  std::vector<Schedule> schedules;
+  int chosen = 0;
+  std::vector<LargeItem> large;  // common to every schedule
+  std::vector<void*> dev_allocs;  // tile lists of the groups (shared between schedules)
 };
 
 namespace {
@@ -255,7 +193,7 @@ struct DeviceGuard {
   }
 };
 
-qft_status check_device(int device) {
+qft_status check_device(int device, int* cus) {
   int count = 0;
   hipError_t e = hipGetDeviceCount(&count);
   if (e != hipSuccess) return hip_fail(e);
@@ -264,6 +202,7 @@ qft_status check_device(int device) {
   e = hipGetDeviceProperties(&prop, device);
   if (e != hipSuccess) return hip_fail(e);
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return QFT_ERROR_UNSUPPORTED;
+  *cus = prop.multiProcessorCount;
   return QFT_SUCCESS;
 }
 
@@ -278,8 +217,7 @@ void free_plan(qft_plan_s* p) {
   if (!p) return;
   if (p->d_sec) (void)hipFree(p->d_sec);
   if (p->d_work) (void)hipFree(p->d_work);
-  if (p->d_tiles) (void)hipFree(p->d_tiles);
-  if (p->d_offs) (void)hipFree(p->d_offs);
+  for (void* a : p->dev_allocs) (void)hipFree(a);
   delete p;
 }
 
@@ -300,42 +238,51 @@ qft_status alloc_common(qft_plan_s* p) {
   return QFT_SUCCESS;
 }
 
+// Grid of a tile group: the resident workgroups (persistent: each strides
+// over the tiles) or one workgroup per tile (the hardware dispatcher hands
+// out tiles as workgroups finish).
+int group_grid(const qft_plan_s* p, int tl, int64_t ntiles, bool persistent) {
+  const int64_t cap = (int64_t)std::max(p->cus, 1) * qftk::tile_wgs_per_cu(tl);
+  return (int)std::max<int64_t>(1, persistent ? std::min<int64_t>(ntiles, cap) : ntiles);
+}
+
+// Uniform batch of N = 2^log2n <= 2^tl in tiles of 2^tl cells.
+qft_status uniform_group(const qft_plan_s* p, int tl, qftk::TileGroup* g) {
+  const int64_t per = (int64_t)1 << (tl - p->log2n);
+  const int64_t ntiles = (p->batch + per - 1) / per;
+  if (ntiles > 0x7fffffff) return QFT_ERROR_INVALID_VALUE;
+  *g = qftk::TileGroup{tl, (int)ntiles, (int)ntiles, nullptr, nullptr, p->log2n, p->batch};
+  return QFT_SUCCESS;
+}
+
+// Uneven transforms with lo <= log2n <= hi in tiles of 2^tl cells.
+qft_status uneven_group(qft_plan_s* p, const int32_t* log2n, const std::vector<int64_t>& offsets,
+                        int lo, int hi, int tl, qftk::TileGroup* g) {
+  std::vector<qftk::TileDesc> desc;
+  std::vector<int64_t> perm;
+  qftk::build_tiles(log2n, offsets, lo, hi, tl, desc, perm);
+  *g = qftk::TileGroup{tl, (int)desc.size(), group_grid(p, tl, (int64_t)desc.size(), true),
+                       nullptr, nullptr, 0, 0};
+  if (desc.empty()) return QFT_SUCCESS;
+  std::vector<int4> tiles;
+  for (const qftk::TileDesc& d : desc) tiles.push_back(make_int4(d.log2n, d.first, d.count, 0));
+  QFT_HIP(hipMalloc(&g->d_tiles, tiles.size() * sizeof(int4)));
+  p->dev_allocs.push_back(g->d_tiles);
+  QFT_HIP(hipMalloc(&g->d_offs, perm.size() * sizeof(int64_t)));
+  p->dev_allocs.push_back(g->d_offs);
+  QFT_HIP(hipMemcpy(g->d_tiles, tiles.data(), tiles.size() * sizeof(int4),
+                    hipMemcpyHostToDevice));
+  QFT_HIP(hipMemcpy(g->d_offs, perm.data(), perm.size() * sizeof(int64_t),
+                    hipMemcpyHostToDevice));
+  return QFT_SUCCESS;
+}
+
 inline unsigned grid_for(int64_t work, int block) {
   int64_t g = (work + block - 1) / block;
   const int64_t cap = 1 << 20;
   if (g > cap) g = cap;
   if (g < 1) g = 1;
   return (unsigned)g;
-}
-
-template <int LOGN, int DT, bool SWAP>
-void launch_tile_s(const void* in, void* out, int64_t batch, const float* sec, hipStream_t st) {
-  using T = typename qftk::Store<DT>::T;
-  constexpr int TL = LOGN <= 12 ? 12 : LOGN;
-  constexpr int BLOCK = TL == 12 ? 256 : (TL == 13 ? 512 : 1024);
-  constexpr int64_t Tmax = (int64_t)1 << (TL - LOGN);
-  const int64_t grid = (batch + Tmax - 1) / Tmax;
-  hipLaunchKernelGGL((qftk::tile_kernel_s<LOGN, TL, BLOCK, DT, SWAP>), dim3((unsigned)grid),
-                     dim3(BLOCK), 0, st, (const T*)in, (T*)out, batch, sec);
-}
-
-template <int DT, bool SWAP>
-qft_status launch_tile(const void* in, void* out, int log2n, int64_t batch, const float* sec,
-                       hipStream_t st) {
-  const int tl = log2n <= 12 ? 12 : log2n;
-  if (((batch + ((int64_t)1 << (tl - log2n)) - 1) >> (tl - log2n)) > 0x7fffffff)
-    return QFT_ERROR_INVALID_VALUE;
-  switch (log2n) {
-#define QFT_TILE_CASE(L) \
-  case L: launch_tile_s<L, DT, SWAP>(in, out, batch, sec, st); break;
-    QFT_TILE_CASE(1) QFT_TILE_CASE(2) QFT_TILE_CASE(3) QFT_TILE_CASE(4) QFT_TILE_CASE(5)
-    QFT_TILE_CASE(6) QFT_TILE_CASE(7) QFT_TILE_CASE(8) QFT_TILE_CASE(9) QFT_TILE_CASE(10)
-    QFT_TILE_CASE(11) QFT_TILE_CASE(12) QFT_TILE_CASE(13) QFT_TILE_CASE(14)
-#undef QFT_TILE_CASE
-    default: return QFT_ERROR_INVALID_SIZE;
-  }
-  hipError_t e = hipGetLastError();
-  return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
 }
 
 // GPU executor of the multi-pass schedule (qft_schedule.hpp).
@@ -434,50 +381,65 @@ qft_status launch_large(const void* in, void* out, int log2n, int64_t batch, con
 }
 
 template <int DT, bool SWAP>
-qft_status launch_uneven(const qft_plan_s* p, const void* in, void* out, hipStream_t st) {
-  using T = typename qftk::Store<DT>::T;
-  const T* x = (const T*)in;
-  T* X = (T*)out;
-  if (p->ntiles > 0) {
-    hipLaunchKernelGGL((qftk::uneven_kernel<kUnevenTileLog2, kUnevenBlock, DT, SWAP>),
-                       dim3(p->persistent_grid), dim3(kUnevenBlock), 0, st, x, X, p->d_tiles,
-                       p->ntiles, p->d_offs, p->d_sec);
-    hipError_t e = hipGetLastError();
+qft_status run_schedule(const qft_plan_s* p, const Schedule& s, const void* in, void* out,
+                        hipStream_t st) {
+  using E = typename qftk::Store<DT>::T;
+  for (const qftk::TileGroup& g : s.groups) {
+    if (g.ntiles == 0) continue;
+    hipError_t e = hipErrorInvalidValue;
+    switch (g.tl) {
+      case 12: e = qftk::launch_tiles<DT, 12, SWAP>(g, in, out, p->d_sec, st); break;
+      case 13: e = qftk::launch_tiles<DT, 13, SWAP>(g, in, out, p->d_sec, st); break;
+      case 14: e = qftk::launch_tiles<DT, 14, SWAP>(g, in, out, p->d_sec, st); break;
+      default: break;
+    }
     if (e != hipSuccess) return hip_fail(e);
   }
+  float2* W0 = p->d_work;
+  float2* W1 = p->d_work + p->work_cells;
   for (const LargeItem& it : p->large) {
-    qft_status s = launch_large<DT, SWAP>(x + it.offset, X + it.offset, it.log2n, 1, p->d_sec,
-                                          p->d_work, p->d_work + p->work_cells, st);
-    if (s != QFT_SUCCESS) return s;
+    const qft_status r = launch_large<DT, SWAP>((const E*)in + it.offset, (E*)out + it.offset,
+                                                it.log2n, it.batch, p->d_sec, W0, W1, st);
+    if (r != QFT_SUCCESS) return r;
   }
   return QFT_SUCCESS;
 }
 
-template <bool SWAP>
-qft_status exec_impl(qft_plan_t plan, const void* in, void* out, void* stream) {
+qft_status check_buffers(const qft_plan_s* plan, const void* in, const void* out) {
   if (!plan || !in || !out) return QFT_ERROR_INVALID_VALUE;
   const int64_t esz = plan->dtype == QFT_C32 ? 8 : 4;
   if (((uintptr_t)in % esz) != 0 || ((uintptr_t)out % esz) != 0) return QFT_ERROR_ALIGNMENT;
   const int64_t bytes = plan->total_points * esz;
   const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
   if (a != b && a < b + (uintptr_t)bytes && b < a + (uintptr_t)bytes) return QFT_ERROR_OVERLAP;
+  return QFT_SUCCESS;
+}
+
+template <bool SWAP>
+qft_status exec_sched(const qft_plan_s* plan, int sched, const void* in, void* out,
+                      hipStream_t st) {
+  const Schedule& s = plan->schedules[sched];
+  return plan->dtype == QFT_C32 ? run_schedule<0, SWAP>(plan, s, in, out, st)
+                                : run_schedule<1, SWAP>(plan, s, in, out, st);
+}
+
+template <bool SWAP>
+qft_status exec_impl(qft_plan_t plan, const void* in, void* out, void* stream) {
+  const qft_status c = check_buffers(plan, in, out);
+  if (c != QFT_SUCCESS) return c;
   DeviceGuard guard(plan->device);
   if (!guard.ok) return hip_fail(hipErrorInvalidDevice);
-  hipStream_t st = (hipStream_t)stream;
-  if (plan->uneven) {
-    return plan->dtype == QFT_C32 ? launch_uneven<0, SWAP>(plan, in, out, st)
-                                  : launch_uneven<1, SWAP>(plan, in, out, st);
+  return exec_sched<SWAP>(plan, plan->chosen, in, out, (hipStream_t)stream);
+}
+
+qft_plan_s* new_plan(int device, qft_dtype dtype, int cus) {
+  qft_plan_s* p = new (std::nothrow) qft_plan_s();
+  if (p) {
+    p->device = device;
+    p->dtype = dtype;
+    p->cus = cus;
   }
-  if (plan->log2n <= kMaxTileLog2) {
-    return plan->dtype == QFT_C32
-               ? launch_tile<0, SWAP>(in, out, plan->log2n, plan->batch, plan->d_sec, st)
-               : launch_tile<1, SWAP>(in, out, plan->log2n, plan->batch, plan->d_sec, st);
-  }
-  float2* W0 = plan->d_work;
-  float2* W1 = plan->d_work + plan->work_cells;
-  return plan->dtype == QFT_C32
-             ? launch_large<0, SWAP>(in, out, plan->log2n, plan->batch, plan->d_sec, W0, W1, st)
-             : launch_large<1, SWAP>(in, out, plan->log2n, plan->batch, plan->d_sec, W0, W1, st);
+  return p;
 }
 
 }  // namespace
@@ -517,20 +479,32 @@ qft_status qft_plan_create(qft_plan_t* plan, int log2n, int64_t batch, qft_dtype
   if (batch <= 0 || (dtype != QFT_C32 && dtype != QFT_C16)) return QFT_ERROR_INVALID_VALUE;
   if (log2n < 1 || log2n > QFT_MAX_LOG2N) return QFT_ERROR_INVALID_SIZE;
   if (batch > ((int64_t)1 << 40) >> log2n) return QFT_ERROR_INVALID_VALUE;
-  qft_status s = check_device(device);
+  int cus = 0;
+  qft_status s = check_device(device, &cus);
   if (s != QFT_SUCCESS) return s;
   DeviceGuard guard(device);
   if (!guard.ok) return hip_fail(hipErrorInvalidDevice);
-  qft_plan_s* p = new (std::nothrow) qft_plan_s();
+  qft_plan_s* p = new_plan(device, dtype, cus);
   if (!p) return QFT_ERROR_ALLOC;
-  p->device = device;
-  p->dtype = dtype;
   p->log2n = log2n;
   p->batch = batch;
   p->max_log2n = log2n;
   add_costs(p, log2n, batch);
-  if (log2n > kMaxTileLog2) p->work_cells = batch << log2n;
-  s = alloc_common(p);
+  if (log2n <= qftk::kMaxTileLog2) {
+    // one schedule per tile size that holds a transform; the smallest first
+    // one workgroup per tile of 2^max(12, log2n) cells
+    const int tl = std::max(qftk::kMinTileLog2, log2n);
+    Schedule sc;
+    sc.name = "t" + std::to_string(tl) + ":" + std::to_string(log2n);
+    sc.groups.resize(1);
+    s = uniform_group(p, tl, &sc.groups[0]);
+    if (s == QFT_SUCCESS) p->schedules.push_back(sc);
+  } else {
+    p->work_cells = batch << log2n;
+    p->large.push_back({log2n, 0, batch});
+    p->schedules.push_back(Schedule{log2n <= 16 ? "two-pass" : "multi-pass", {}});
+  }
+  if (s == QFT_SUCCESS) s = alloc_common(p);
   if (s != QFT_SUCCESS) {
     free_plan(p);
     return s;
@@ -548,52 +522,86 @@ qft_status qft_plan_create_uneven(qft_plan_t* plan, const int32_t* log2n, int64_
   if (count > (1 << 30)) return QFT_ERROR_INVALID_VALUE;
   for (int64_t i = 0; i < count; ++i)
     if (log2n[i] < 1 || log2n[i] > QFT_MAX_LOG2N) return QFT_ERROR_INVALID_SIZE;
-  qft_status s = check_device(device);
+  int cus = 0;
+  qft_status s = check_device(device, &cus);
   if (s != QFT_SUCCESS) return s;
   DeviceGuard guard(device);
   if (!guard.ok) return hip_fail(hipErrorInvalidDevice);
-  qft_plan_s* p = new (std::nothrow) qft_plan_s();
+  qft_plan_s* p = new_plan(device, dtype, cus);
   if (!p) return QFT_ERROR_ALLOC;
-  p->device = device;
-  p->dtype = dtype;
   p->uneven = true;
+  bool has[QFT_MAX_LOG2N + 1] = {};
   for (int64_t i = 0; i < count; ++i) {
     p->max_log2n = std::max(p->max_log2n, (int)log2n[i]);
+    has[log2n[i]] = true;
     add_costs(p, log2n[i], 1);
   }
   if (p->total_points > ((int64_t)1 << 40)) {
     free_plan(p);
     return QFT_ERROR_INVALID_VALUE;
   }
-  std::vector<int64_t> off, perm, large_idx;
-  std::vector<qftk::TileDesc> tdesc;
-  qftk::build_uneven_worklist(log2n, count, kUnevenTileLog2, off, tdesc, perm, large_idx);
-  std::vector<int4> tiles;
-  for (const qftk::TileDesc& d : tdesc) tiles.push_back(make_int4(d.log2n, d.first, d.count, 0));
-  int64_t large_max = 0;
-  for (int64_t i : large_idx) {
-    p->large.push_back({log2n[i], off[i]});
-    large_max = std::max<int64_t>(large_max, (int64_t)1 << log2n[i]);
+  std::vector<int64_t> off;
+  qftk::packed_offsets(log2n, count, off);
+  // transforms beyond one workgroup, largest first
+  std::vector<int64_t> big;
+  for (int64_t i = 0; i < count; ++i)
+    if (log2n[i] > qftk::kMaxTileLog2) big.push_back(i);
+  std::stable_sort(big.begin(), big.end(),
+                   [&](int64_t a, int64_t b) { return log2n[a] > log2n[b]; });
+  for (int64_t i : big) {
+    p->large.push_back({log2n[i], off[i], 1});
+    p->work_cells = std::max<int64_t>(p->work_cells, (int64_t)1 << log2n[i]);
   }
-  p->work_cells = large_max;
-  s = alloc_common(p);
-  if (s == QFT_SUCCESS && !tiles.empty()) {
-    p->ntiles = (int)tiles.size();
-    hipError_t e = hipMalloc(&p->d_tiles, tiles.size() * sizeof(int4));
-    if (e == hipSuccess) e = hipMalloc(&p->d_offs, perm.size() * sizeof(int64_t));
-    if (e == hipSuccess)
-      e = hipMemcpy(p->d_tiles, tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-      e = hipMemcpy(p->d_offs, perm.data(), perm.size() * sizeof(int64_t), hipMemcpyHostToDevice);
-    if (e != hipSuccess) s = hip_fail(e);
-    int cus = 0;
-    if (s == QFT_SUCCESS) {
-      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-      if (e != hipSuccess) s = hip_fail(e);
+  // Candidate schedules: tile size for N <= 2^12, for 2^13 and for 2^14; sizes
+  // with the same tile size share one launch.  Each comes with a resident
+  // (persistent) grid and, as "<name>/all", with one workgroup per tile.  The
+  // first one runs every N <= 2^14 in a single persistent launch.
+  const int cand[4][3] = {{14, 14, 14}, {13, 13, 14}, {12, 14, 14}, {12, 13, 14}};
+  std::vector<Schedule> persistent;
+  for (int c = 0; c < 4 && s == QFT_SUCCESS; ++c) {
+    int tl_of[qftk::kMaxTileLog2 + 1];
+    for (int r = 1; r <= qftk::kMaxTileLog2; ++r)
+      tl_of[r] = r <= 12 ? cand[c][0] : (r == 13 ? cand[c][1] : cand[c][2]);
+    // launches: maximal runs of present sizes with the same tile size
+    std::vector<int> lo_hi;
+    std::string name;
+    for (int r = 1; r <= qftk::kMaxTileLog2; ++r) {
+      if (!has[r]) continue;
+      if (!lo_hi.empty() && tl_of[lo_hi[lo_hi.size() - 2]] == tl_of[r]) {
+        lo_hi.back() = r;
+      } else {
+        lo_hi.push_back(r);
+        lo_hi.push_back(r);
+      }
     }
-    // one 128 KiB-LDS workgroup fits per CU
-    p->persistent_grid = std::max(1, std::min(p->ntiles, cus));
+    for (size_t k = 0; k < lo_hi.size(); k += 2) {
+      const int lo = lo_hi[k], hi = lo_hi[k + 1];
+      if (!name.empty()) name += "+";
+      name += "t" + std::to_string(tl_of[lo]) + ":" + std::to_string(lo) +
+              (hi > lo ? "-" + std::to_string(hi) : "");
+    }
+    if (name.empty()) name = "large-only";
+    bool dup = false;
+    for (const Schedule& o : persistent) dup |= o.name == name;
+    if (dup) continue;
+    Schedule sc;
+    sc.name = name;
+    for (size_t k = 0; k < lo_hi.size() && s == QFT_SUCCESS; k += 2) {
+      qftk::TileGroup g{};
+      s = uneven_group(p, log2n, off, lo_hi[k], lo_hi[k + 1], tl_of[lo_hi[k]], &g);
+      sc.groups.push_back(g);
+    }
+    persistent.push_back(sc);
   }
+  for (const Schedule& sc : persistent) p->schedules.push_back(sc);
+  for (const Schedule& sc : persistent) {
+    if (sc.groups.empty()) continue;
+    Schedule all = sc;
+    all.name += "/all";
+    for (qftk::TileGroup& g : all.groups) g.grid = std::max(g.ntiles, 1);
+    p->schedules.push_back(all);
+  }
+  if (s == QFT_SUCCESS) s = alloc_common(p);
   if (s != QFT_SUCCESS) {
     free_plan(p);
     return s;
@@ -625,6 +633,70 @@ qft_status qft_plan_info(qft_plan_t plan, int64_t* total_points, int64_t* algo_b
   if (algo_bytes) *algo_bytes = 2 * plan->total_points * esz;
   if (flops_5nlogn) *flops_5nlogn = plan->flops_5nlogn;
   if (flops_actual) *flops_actual = plan->flops_actual;
+  return QFT_SUCCESS;
+}
+
+qft_status qft_plan_schedules(qft_plan_t plan, int* count, int* chosen) {
+  if (!plan) return QFT_ERROR_INVALID_VALUE;
+  if (count) *count = (int)plan->schedules.size();
+  if (chosen) *chosen = plan->chosen;
+  return QFT_SUCCESS;
+}
+
+const char* qft_plan_schedule_name(qft_plan_t plan, int schedule) {
+  if (!plan || schedule < 0 || schedule >= (int)plan->schedules.size()) return nullptr;
+  return plan->schedules[schedule].name.c_str();
+}
+
+qft_status qft_plan_set_schedule(qft_plan_t plan, int schedule) {
+  if (!plan || schedule < 0 || schedule >= (int)plan->schedules.size())
+    return QFT_ERROR_INVALID_VALUE;
+  plan->chosen = schedule;
+  return QFT_SUCCESS;
+}
+
+qft_status qft_plan_autotune(qft_plan_t plan, const void* in, void* out, void* stream, int reps,
+                             double* ms, int ms_len, int* chosen) {
+  qft_status c = check_buffers(plan, in, out);
+  if (c != QFT_SUCCESS) return c;
+  if (reps < 1 || reps > 10000 || ms_len < 0 || (ms_len > 0 && !ms))
+    return QFT_ERROR_INVALID_VALUE;
+  DeviceGuard guard(plan->device);
+  if (!guard.ok) return hip_fail(hipErrorInvalidDevice);
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  QFT_HIP(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e);
+  }
+  int best = -1;
+  float best_ms = 0.f;
+  for (int i = 0; i < (int)plan->schedules.size() && c == QFT_SUCCESS; ++i) {
+    c = exec_sched<false>(plan, i, in, out, st);  // warm-up
+    if (c == QFT_SUCCESS) e = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && c == QFT_SUCCESS && e == hipSuccess; ++r)
+      c = exec_sched<false>(plan, i, in, out, st);
+    if (c == QFT_SUCCESS && e == hipSuccess) e = hipEventRecord(e1, st);
+    if (c == QFT_SUCCESS && e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (c == QFT_SUCCESS && e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (c == QFT_SUCCESS && e != hipSuccess) c = hip_fail(e);
+    if (c == QFT_SUCCESS) {
+      t /= (float)reps;
+      if (i < ms_len) ms[i] = t;
+      if (best < 0 || t < best_ms) {
+        best = i;
+        best_ms = t;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (c != QFT_SUCCESS) return c;
+  plan->chosen = best;
+  if (chosen) *chosen = best;
   return QFT_SUCCESS;
 }
 

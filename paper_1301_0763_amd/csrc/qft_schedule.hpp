@@ -67,29 +67,27 @@ struct TileDesc {
   int count;
 };
 
-// Work list of an uneven plan.  Transforms with log2n <= tile_log2 are grouped
-// by size, largest size first, into tiles of at most 2^(tile_log2 - log2n)
-// transforms; `perm` lists their element offsets tile by tile.  Longer
-// transforms go to `large` (index, largest first).  `offsets` receives the
-// packed layout (exclusive prefix sum of 2^log2n[i]).
-inline void build_uneven_worklist(const int32_t* log2n, int64_t count, int tile_log2,
-                                  std::vector<int64_t>& offsets, std::vector<TileDesc>& tiles,
-                                  std::vector<int64_t>& perm, std::vector<int64_t>& large) {
+// Packed layout of an uneven batch: offsets[i] = sum of 2^log2n[j], j < i.
+inline void packed_offsets(const int32_t* log2n, int64_t count, std::vector<int64_t>& offsets) {
   offsets.assign(count, 0);
   int64_t acc = 0;
   for (int64_t i = 0; i < count; ++i) {
     offsets[i] = acc;
     acc += (int64_t)1 << log2n[i];
   }
-  tiles.clear();
-  perm.clear();
-  large.clear();
-  std::vector<std::vector<int64_t>> cls(tile_log2 + 1);
-  for (int64_t i = 0; i < count; ++i) {
-    if (log2n[i] <= tile_log2) cls[log2n[i]].push_back(offsets[i]);
-    else large.push_back(i);
-  }
-  for (int lg = tile_log2; lg >= 1; --lg) {
+}
+
+// Tiles of 2^tile_log2 cells for the transforms with lo <= log2n[i] <= hi
+// (hi <= tile_log2), grouped by size, largest size first, each tile at most
+// 2^(tile_log2 - log2n) transforms of one size; `perm` receives their element
+// offsets tile by tile.  Appends to tiles/perm.
+inline void build_tiles(const int32_t* log2n, const std::vector<int64_t>& offsets, int lo,
+                        int hi, int tile_log2, std::vector<TileDesc>& tiles,
+                        std::vector<int64_t>& perm) {
+  std::vector<std::vector<int64_t>> cls(hi + 1);
+  for (size_t i = 0; i < offsets.size(); ++i)
+    if (log2n[i] >= lo && log2n[i] <= hi) cls[log2n[i]].push_back(offsets[i]);
+  for (int lg = hi; lg >= lo; --lg) {
     const size_t per_tile = (size_t)1 << (tile_log2 - lg);
     for (size_t a = 0; a < cls[lg].size(); a += per_tile) {
       const int cnt = (int)std::min(per_tile, cls[lg].size() - a);
@@ -97,6 +95,21 @@ inline void build_uneven_worklist(const int32_t* log2n, int64_t count, int tile_
       for (int q = 0; q < cnt; ++q) perm.push_back(cls[lg][a + q]);
     }
   }
+}
+
+// Work list of an uneven plan with one tile size: transforms with
+// log2n <= tile_log2 go to tiles (build_tiles), longer ones to `large`
+// (index, largest first).
+inline void build_uneven_worklist(const int32_t* log2n, int64_t count, int tile_log2,
+                                  std::vector<int64_t>& offsets, std::vector<TileDesc>& tiles,
+                                  std::vector<int64_t>& perm, std::vector<int64_t>& large) {
+  packed_offsets(log2n, count, offsets);
+  tiles.clear();
+  perm.clear();
+  large.clear();
+  build_tiles(log2n, offsets, 1, tile_log2, tile_log2, tiles, perm);
+  for (int64_t i = 0; i < count; ++i)
+    if (log2n[i] > tile_log2) large.push_back(i);
   std::stable_sort(large.begin(), large.end(),
                    [&](int64_t a, int64_t b) { return log2n[a] > log2n[b]; });
 }

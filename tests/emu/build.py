@@ -34,8 +34,8 @@ def load():
     L.emu_tile.argtypes = [i, i, vp, vp, i, i, i]
     L.emu_multipass.argtypes = [i, i, vp, vp, i, i64, i, i]
     L.emu_uneven.argtypes = [i, i, vp, vp, ctypes.POINTER(ctypes.c_int32), i64, i, i, i]
-    L.emu_twopass.argtypes = [i, i, vp, vp, i, i64, i]
-    L.emu_tile_s.argtypes = [i, i, vp, vp, i, i]
+    L.emu_twopass.argtypes = [i, i, vp, vp, i, i64]
+    L.emu_tile_s.argtypes = [i, i, vp, vp, i, i, vp]
     for f in (L.emu_tile, L.emu_multipass, L.emu_uneven, L.emu_twopass, L.emu_tile_s):
         f.restype = i
     return L

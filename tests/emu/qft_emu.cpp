@@ -130,7 +130,7 @@ constexpr int kEmuWave = 32;  // emulated wavefront width (wave-level chain phas
 // The specialised tile kernel exactly as launched on the GPU: LOGN <= 12 uses
 // 2^12-cell tiles of 256 threads, 13 uses 512 threads, 14 uses 1024.
 template <int DT, bool SWAP, int LOGN>
-int tile_s_impl(const void* x, void* X, int Tact, const float* sec) {
+int tile_s_impl(const void* x, void* X, int Tact, const float* sec, const int64_t* offs) {
   using E = typename qftk::Store<DT>::T;
   constexpr int TL = LOGN <= 12 ? 12 : LOGN;
   constexpr int NT = TL == 12 ? 256 : (TL == 13 ? 512 : 1024);
@@ -141,29 +141,35 @@ int tile_s_impl(const void* x, void* X, int Tact, const float* sec) {
   Tracker tr(NT);
   TPtr W{lds.data(), 0, &tr, cells, kEmuPad};
   run_workgroup(NT, tr, [&](int tid, auto sync) {
-    qftk::tile_body_s<DT, SWAP, LOGN, T, NT, 64>((const E*)x, (E*)X, W, Tact, sec, tid, sync,
-                                                 sync);
+    if (offs) {
+      const qftk::GatherIO<DT, SWAP> io((const E*)x, (E*)X, offs);
+      qftk::tile_body_s<LOGN, T, NT, 64>(io, W, Tact, sec, tid, sync, sync);
+    } else {
+      const qftk::ContigIO<DT, SWAP, LOGN> io((const E*)x, (E*)X);
+      qftk::tile_body_s<LOGN, T, NT, 64>(io, W, Tact, sec, tid, sync, sync);
+    }
   });
   return tr.oob ? -100 : (int)tr.races;
 }
 
 template <int DT, bool SWAP>
-int tile_s_dispatch(const void* x, void* X, int logn, int Tact, const float* sec) {
+int tile_s_dispatch(const void* x, void* X, int logn, int Tact, const float* sec,
+                    const int64_t* offs) {
   switch (logn) {
-    case 1: return tile_s_impl<DT, SWAP, 1>(x, X, Tact, sec);
-    case 2: return tile_s_impl<DT, SWAP, 2>(x, X, Tact, sec);
-    case 3: return tile_s_impl<DT, SWAP, 3>(x, X, Tact, sec);
-    case 4: return tile_s_impl<DT, SWAP, 4>(x, X, Tact, sec);
-    case 5: return tile_s_impl<DT, SWAP, 5>(x, X, Tact, sec);
-    case 6: return tile_s_impl<DT, SWAP, 6>(x, X, Tact, sec);
-    case 7: return tile_s_impl<DT, SWAP, 7>(x, X, Tact, sec);
-    case 8: return tile_s_impl<DT, SWAP, 8>(x, X, Tact, sec);
-    case 9: return tile_s_impl<DT, SWAP, 9>(x, X, Tact, sec);
-    case 10: return tile_s_impl<DT, SWAP, 10>(x, X, Tact, sec);
-    case 11: return tile_s_impl<DT, SWAP, 11>(x, X, Tact, sec);
-    case 12: return tile_s_impl<DT, SWAP, 12>(x, X, Tact, sec);
-    case 13: return tile_s_impl<DT, SWAP, 13>(x, X, Tact, sec);
-    case 14: return tile_s_impl<DT, SWAP, 14>(x, X, Tact, sec);
+    case 1: return tile_s_impl<DT, SWAP, 1>(x, X, Tact, sec, offs);
+    case 2: return tile_s_impl<DT, SWAP, 2>(x, X, Tact, sec, offs);
+    case 3: return tile_s_impl<DT, SWAP, 3>(x, X, Tact, sec, offs);
+    case 4: return tile_s_impl<DT, SWAP, 4>(x, X, Tact, sec, offs);
+    case 5: return tile_s_impl<DT, SWAP, 5>(x, X, Tact, sec, offs);
+    case 6: return tile_s_impl<DT, SWAP, 6>(x, X, Tact, sec, offs);
+    case 7: return tile_s_impl<DT, SWAP, 7>(x, X, Tact, sec, offs);
+    case 8: return tile_s_impl<DT, SWAP, 8>(x, X, Tact, sec, offs);
+    case 9: return tile_s_impl<DT, SWAP, 9>(x, X, Tact, sec, offs);
+    case 10: return tile_s_impl<DT, SWAP, 10>(x, X, Tact, sec, offs);
+    case 11: return tile_s_impl<DT, SWAP, 11>(x, X, Tact, sec, offs);
+    case 12: return tile_s_impl<DT, SWAP, 12>(x, X, Tact, sec, offs);
+    case 13: return tile_s_impl<DT, SWAP, 13>(x, X, Tact, sec, offs);
+    case 14: return tile_s_impl<DT, SWAP, 14>(x, X, Tact, sec, offs);
     default: return -1;
   }
 }
@@ -308,53 +314,30 @@ int uneven_impl(const void* x, void* X, const int32_t* log2n, int64_t count, int
 }
 
 template <int DT, bool SWAP, int MC_LOG2>
-int twopass_mc(const void* x, void* X, int64_t batch, int variant) {
-  const bool both = variant == 1;
+int twopass_mc(const void* x, void* X, int64_t batch) {
   using E = typename qftk::Store<DT>::T;
   constexpr int MC = 1 << MC_LOG2;
-  // threads per workgroup: the GPU's 256 for 2^12-cell segments, else <= 32
-  constexpr int NT = MC_LOG2 >= 12 ? 256 : (MC < 32 ? MC : 32);
-  const int nthr = NT;
+  // threads per workgroup: the GPU's 512 for 2^12-cell segments, else <= 32
+  constexpr int NT = MC_LOG2 >= 12 ? 512 : (MC < 32 ? MC : 32);
   constexpr int logn = MC_LOG2 + 3;
   const int64_t cells = batch << logn;
   std::vector<float> sec = secants(logn);
   std::vector<float2> heap(cells, make_float2(0.f, 0.f));
   int64_t races = 0;
-  // pass A: 8 workgroups per transform
+  // pass A: both sides of one segment per workgroup, 4 workgroups per transform
   for (int64_t t = 0; t < batch; ++t) {
-    for (int w = 0; w < 8; ++w) {
-      const int64_t lc = MC + 1;
+    for (int j = 0; j < 4; ++j) {
+      const int64_t lc = 2 * MC + 1;
       std::vector<float2> lds(lc + (lc >> kEmuPad));
-      Tracker ltr(nthr);
+      Tracker ltr(NT);
       TPtr L{lds.data(), 0, &ltr, lc, kEmuPad};
       const E* xt = (const E*)x + (t << logn);
       float2* wt = heap.data() + (t << logn);
-      run_workgroup(nthr, ltr, [&](int tid, auto sync) {
-        qftk::tp_pass_a<DT, SWAP, MC_LOG2, NT>(xt, wt, L, w, sec.data(), tid, kEmuWave, sync,
-                                               sync);
+      run_workgroup(NT, ltr, [&](int tid, auto sync) {
+        qftk::tp_pass_a2<DT, SWAP, MC_LOG2, NT, 64>(xt, wt, L, j, sec.data(), tid, sync, sync);
       });
-      if (ltr.oob) return -100;
+      if (ltr.oob) return -102;
       races += ltr.races;
-    }
-  }
-  if (both) {  // redo pass A with both sides per workgroup (4 workgroups)
-    std::fill(heap.begin(), heap.end(), make_float2(0.f, 0.f));
-    constexpr int NT2 = MC_LOG2 >= 12 ? 512 : (MC < 32 ? MC : 32);
-    for (int64_t t = 0; t < batch; ++t) {
-      for (int j = 0; j < 4; ++j) {
-        const int64_t lc = 2 * MC + 1;
-        std::vector<float2> lds(lc + (lc >> kEmuPad));
-        Tracker ltr(NT2);
-        TPtr L{lds.data(), 0, &ltr, lc, kEmuPad};
-        const E* xt = (const E*)x + (t << logn);
-        float2* wt = heap.data() + (t << logn);
-        run_workgroup(NT2, ltr, [&](int tid, auto sync) {
-          qftk::tp_pass_a2<DT, SWAP, MC_LOG2, NT2>(xt, wt, L, j, sec.data(), tid, kEmuWave, sync,
-                                                   sync);
-        });
-        if (ltr.oob) return -102;
-        races += ltr.races;
-      }
     }
   }
   // pass B: N/8 items per transform, tracked reads of the heap buffer
@@ -373,13 +356,14 @@ int twopass_mc(const void* x, void* X, int64_t batch, int variant) {
 }
 
 template <int DT, bool SWAP>
-int twopass_impl(const void* x, void* X, int mc_log2, int64_t batch, int nthr) {
+int twopass_impl(const void* x, void* X, int mc_log2, int64_t batch) {
   switch (mc_log2) {
-    case 3: return twopass_mc<DT, SWAP, 3>(x, X, batch, nthr);
-    case 4: return twopass_mc<DT, SWAP, 4>(x, X, batch, nthr);
-    case 5: return twopass_mc<DT, SWAP, 5>(x, X, batch, nthr);
-    case 7: return twopass_mc<DT, SWAP, 7>(x, X, batch, nthr);
-    case 12: return twopass_mc<DT, SWAP, 12>(x, X, batch, nthr);
+    case 3: return twopass_mc<DT, SWAP, 3>(x, X, batch);
+    case 4: return twopass_mc<DT, SWAP, 4>(x, X, batch);
+    case 5: return twopass_mc<DT, SWAP, 5>(x, X, batch);
+    case 7: return twopass_mc<DT, SWAP, 7>(x, X, batch);
+    case 10: return twopass_mc<DT, SWAP, 10>(x, X, batch);
+    case 12: return twopass_mc<DT, SWAP, 12>(x, X, batch);
     default: return -5;
   }
 }
@@ -388,13 +372,13 @@ int twopass_impl(const void* x, void* X, int mc_log2, int64_t batch, int nthr) {
 
 extern "C" {
 
-// variant 0: one side per pass-A workgroup; 1: both sides per workgroup.
-int emu_twopass(int dt, int swap, const void* x, void* X, int mc_log2, int64_t batch, int nthr) {
-  if (batch < 1 || nthr < 0 || nthr > 1) return -1;
-  if (dt == 0) return swap ? twopass_impl<0, true>(x, X, mc_log2, batch, nthr)
-                           : twopass_impl<0, false>(x, X, mc_log2, batch, nthr);
-  return swap ? twopass_impl<1, true>(x, X, mc_log2, batch, nthr)
-              : twopass_impl<1, false>(x, X, mc_log2, batch, nthr);
+// Two-pass path with segments of 2^mc_log2 cells (N = 8 * 2^mc_log2).
+int emu_twopass(int dt, int swap, const void* x, void* X, int mc_log2, int64_t batch) {
+  if (batch < 1) return -1;
+  if (dt == 0) return swap ? twopass_impl<0, true>(x, X, mc_log2, batch)
+                           : twopass_impl<0, false>(x, X, mc_log2, batch);
+  return swap ? twopass_impl<1, true>(x, X, mc_log2, batch)
+              : twopass_impl<1, false>(x, X, mc_log2, batch);
 }
 
 
@@ -407,13 +391,16 @@ int emu_tile(int dt, int swap, const void* x, void* X, int logn, int T, int nthr
               : tile_impl<1, false>(x, X, logn, T, nullptr, sec.data(), nthr);
 }
 
-// One workgroup of the specialised GPU tile kernel (Tact transforms).
-int emu_tile_s(int dt, int swap, const void* x, void* X, int logn, int Tact) {
+// One workgroup of the specialised GPU tile kernel (Tact transforms): a
+// contiguous batch, or, with offs != NULL, transforms at element offsets
+// offs[0 .. Tact) (the persistent kernel of uneven plans).
+int emu_tile_s(int dt, int swap, const void* x, void* X, int logn, int Tact,
+               const int64_t* offs) {
   std::vector<float> sec = secants(logn < 3 ? 3 : logn);
-  if (dt == 0) return swap ? tile_s_dispatch<0, true>(x, X, logn, Tact, sec.data())
-                           : tile_s_dispatch<0, false>(x, X, logn, Tact, sec.data());
-  return swap ? tile_s_dispatch<1, true>(x, X, logn, Tact, sec.data())
-              : tile_s_dispatch<1, false>(x, X, logn, Tact, sec.data());
+  if (dt == 0) return swap ? tile_s_dispatch<0, true>(x, X, logn, Tact, sec.data(), offs)
+                           : tile_s_dispatch<0, false>(x, X, logn, Tact, sec.data(), offs);
+  return swap ? tile_s_dispatch<1, true>(x, X, logn, Tact, sec.data(), offs)
+              : tile_s_dispatch<1, false>(x, X, logn, Tact, sec.data(), offs);
 }
 
 int emu_multipass(int dt, int swap, const void* x, void* X, int logn, int64_t batch,

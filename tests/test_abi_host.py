@@ -141,3 +141,15 @@ def test_secant_table_base_constant():
     # nested sizes: the table for a smaller N is a prefix of a larger one
     big = np.frombuffer(qft.qft_secant_table(12), dtype=np.float32)
     assert np.array_equal(big[:t.size], t)
+
+
+def test_schedule_entry_points_reject_null_plan():
+    L = _lib.lib()
+    n, c = ctypes.c_int(), ctypes.c_int()
+    assert L.qft_plan_schedules(None, ctypes.byref(n), ctypes.byref(c)) == \
+        _lib.QFT_ERROR_INVALID_VALUE
+    assert L.qft_plan_schedule_name(None, 0) is None
+    assert L.qft_plan_set_schedule(None, 0) == _lib.QFT_ERROR_INVALID_VALUE
+    ms = (ctypes.c_double * 4)()
+    assert L.qft_plan_autotune(None, 8, 8, None, 5, ms, 4, ctypes.byref(c)) == \
+        _lib.QFT_ERROR_INVALID_VALUE

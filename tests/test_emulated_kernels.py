@@ -156,36 +156,35 @@ def test_uneven_worklist(emu):
         off += N
 
 
-def run_tp(emu, x, mc_log2, variant=1, swap=0):
-    """variant 0: one side per pass-A workgroup; 1: both sides (as launched)."""
+def run_tp(emu, x, mc_log2, swap=0):
     xf = _as_c64(x)
     out = np.zeros_like(xf)
-    races = emu.emu_twopass(0, swap, xf.ctypes.data, out.ctypes.data, mc_log2, xf.shape[0],
-                            variant)
+    races = emu.emu_twopass(0, swap, xf.ctypes.data, out.ctypes.data, mc_log2, xf.shape[0])
     assert races >= 0, races
     return races, out
 
 
-@pytest.mark.parametrize("mc_log2", [3, 4, 5, 7])
+@pytest.mark.parametrize("mc_log2", [3, 4, 5, 7, 10])
 @pytest.mark.parametrize("swap", [0, 1])
-@pytest.mark.parametrize("variant", [0, 1])
-def test_two_pass_small(emu, mc_log2, swap, variant):
-    """Two-pass path (N = 8 * segment) with small segments: gather with the
-    fold and the top round from x, per-segment rounds and head chains in LDS,
-    then the streaming top backward round, chain levels N/2 and N, combine."""
+def test_two_pass_small(emu, mc_log2, swap):
+    """Two-pass path (N = 8 * segment) with small segments: pass A gathers
+    both sides of a segment with the fold and the top round from x, runs the
+    segment's remaining rounds (and, for the head, the DCT-0/DST-0 chain up to
+    P = 2 * segment) in LDS; pass B streams the top backward round, chain
+    levels N/2 and N and the combine."""
     logn = mc_log2 + 3
     x = workloads.normal(500 + mc_log2, (3, 1 << logn))
-    races, out = run_tp(emu, x, mc_log2, variant=variant, swap=swap)
+    races, out = run_tp(emu, x, mc_log2, swap=swap)
     assert races == 0
     assert D.relative_l2(out, _ref(x, swap=bool(swap))).max() <= _tol(logn)
 
 
 @pytest.mark.slow
 def test_two_pass_library_size(emu):
-    """N = 2^15 with the library's 2^12-cell segments (512 threads, both sides
-    per workgroup, as launched)."""
+    """N = 2^15 with the library's 2^12-cell segments (512 threads, as
+    launched)."""
     x = workloads.normal(15, (1, 1 << 15))
-    races, out = run_tp(emu, x, 12, variant=1)
+    races, out = run_tp(emu, x, 12)
     assert races == 0
     assert D.relative_l2(out, _ref(x)).max() <= _tol(15)
 
@@ -201,7 +200,7 @@ def test_specialised_tile_as_launched(emu, logn):
         x = workloads.uniform(700 + logn + Tact, (Tact, N))
         xf = _as_c64(x)
         out = np.zeros_like(xf)
-        races = emu.emu_tile_s(0, 0, xf.ctypes.data, out.ctypes.data, logn, Tact)
+        races = emu.emu_tile_s(0, 0, xf.ctypes.data, out.ctypes.data, logn, Tact, None)
         assert races == 0, races
         assert D.relative_l2(out, _ref(x)).max() <= _tol(max(logn, 1))
 
@@ -212,11 +211,37 @@ def test_specialised_tile_adjoint_and_fp16(emu, logn):
     x = workloads.uniform(800 + logn, (1, N))
     xf = _as_c64(x)
     out = np.zeros_like(xf)
-    assert emu.emu_tile_s(0, 1, xf.ctypes.data, out.ctypes.data, logn, 1) == 0
+    assert emu.emu_tile_s(0, 1, xf.ctypes.data, out.ctypes.data, logn, 1, None) == 0
     assert D.relative_l2(out, _ref(x, swap=True)).max() <= _tol(logn)
     x16 = np.stack([x.real, x.imag], -1).astype(np.float16)
     o16 = np.zeros_like(x16)
-    assert emu.emu_tile_s(1, 0, x16.ctypes.data, o16.ctypes.data, logn, 1) == 0
+    assert emu.emu_tile_s(1, 0, x16.ctypes.data, o16.ctypes.data, logn, 1, None) == 0
     xin = x16[..., 0].astype(np.float64) + 1j * x16[..., 1].astype(np.float64)
     got = o16[..., 0].astype(np.float64) + 1j * o16[..., 1].astype(np.float64)
     assert D.relative_l2(got, Q.qft(xin)).max() < 1e-3
+
+
+@pytest.mark.parametrize("logn", [3, 7, 10, 12])
+@pytest.mark.parametrize("swap", [0, 1])
+def test_specialised_tile_offset_list(emu, logn, swap):
+    """The persistent kernel of uneven plans: the same specialised body with
+    transform t read from and written to element offset offs[t] (here a
+    scrambled order with gaps that other transforms' data fill)."""
+    N = 1 << logn
+    T = max(1, 4096 // N) if logn <= 12 else 1
+    Tact = max(1, T - 1)
+    rng = np.random.default_rng(logn)
+    slots = rng.permutation(Tact + 2)[:Tact]  # transforms at scattered slots
+    offs = np.ascontiguousarray((slots * N).astype(np.int64))
+    x = workloads.uniform(900 + logn, ((Tact + 2) * N,))
+    xf = _as_c64(x)
+    out = np.full_like(xf, np.nan)
+    races = emu.emu_tile_s(0, swap, xf.ctypes.data, out.ctypes.data, logn, Tact,
+                           offs.ctypes.data)
+    assert races == 0
+    sig = np.stack([x[o:o + N] for o in offs])
+    got = np.stack([out[o:o + N] for o in offs])
+    assert D.relative_l2(got, _ref(sig, swap=bool(swap))).max() <= _tol(logn)
+    # slots that hold no transform of the tile are left untouched
+    free = np.setdiff1d(np.arange(Tact + 2), slots)
+    assert np.all(np.isnan(out[free[0] * N:(free[0] + 1) * N]))

@@ -288,3 +288,55 @@ def test_graph_capture_replays(kind):
         assert torch.equal(out, eager), f"replay {rep} differs"
         del junk
     plan.close()
+
+
+@pytest.mark.parametrize("logn,B", [(5, 300), (10, 37), (12, 9), (13, 5), (14, 3)])
+def test_uniform_and_uneven_kernels_agree(logn, B):
+    """A batch of one size through a uniform plan (contiguous single-size
+    kernel) and through an uneven plan (persistent kernel with an offset
+    list, every schedule) gives bit-identical output: the same specialised
+    body computes both."""
+    say(f"uniform vs uneven kernel: N=2^{logn} B={B}")
+    x = workloads.normal(4000 + logn, (B, 1 << logn))
+    xt = torch.from_numpy(x).to(DEV)
+    ref = qft.Plan(logn, B).forward(xt)
+    up = qft.UnevenPlan([logn] * B)
+    flat = xt.reshape(-1)
+    for i in range(len(up.schedules)):
+        up.schedule = i
+        assert torch.equal(up.forward(flat).reshape(B, -1), ref), up.schedules[i]
+    torch.cuda.synchronize()
+    err = D.relative_l2(ref.cpu().numpy(), ref_fwd(x)).max()
+    assert err <= tol(logn), err
+    up.close()
+
+
+def test_uneven_schedules_and_autotune():
+    """The uneven plan's schedules (one persistent launch for every size, or
+    one launch per tile size) agree bit for bit, the adjoint too; autotune
+    times them all and keeps one."""
+    say("schedules: uneven c4 sizes")
+    r, vals = workloads.make("c4")
+    xt = torch.from_numpy(vals).to(DEV)
+    plan = qft.UnevenPlan(r.tolist())
+    names = plan.schedules
+    say(f"uneven schedules {names}")
+    assert names[0] == "t14:6-14" and len(names) == 8
+    fw, bw = [], []
+    for i in range(len(names)):
+        plan.schedule = i
+        fw.append(plan.forward(xt))
+        bw.append(plan.adjoint(xt))
+    torch.cuda.synchronize()
+    for o in fw[1:]:
+        assert torch.equal(o, fw[0])
+    for o in bw[1:]:
+        assert torch.equal(o, bw[0])
+    times = plan.autotune(xt, reps=3)
+    say(f"autotune ms {times}")
+    assert set(times) == set(names) and all(t > 0 for t in times.values())
+    assert plan.schedules[plan.schedule] == min(times, key=times.get)
+    assert torch.equal(plan.forward(xt), fw[0])
+    with pytest.raises(qft.QFTError):
+        plan.schedule = len(names)
+    plan.close()
