@@ -364,6 +364,7 @@ int twopass_impl(const void* x, void* X, int mc_log2, int64_t batch) {
     case 7: return twopass_mc<DT, SWAP, 7>(x, X, batch);
     case 10: return twopass_mc<DT, SWAP, 10>(x, X, batch);
     case 12: return twopass_mc<DT, SWAP, 12>(x, X, batch);
+    case 13: return twopass_mc<DT, SWAP, 13>(x, X, batch);
     default: return -5;
   }
 }
