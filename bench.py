@@ -142,6 +142,19 @@ def extra_workloads(dev, stream):
     }
     up.close()
     up16.close()
+    # real input (rdft): 8192 real signals of N = 2^12 (two per transform slot)
+    xr = torch.from_numpy(workloads.normal(5, (8192, 4096)).real.astype(np.float32)).to(dev)
+    rp = qft.RealPlan(12, 8192)
+    hr = torch.empty(8192, 2049, dtype=torch.complex64, device=dev)
+    rms = time_ms(lambda: qft.qft_exec_rdft(rp.handle, xr.data_ptr(), hr.data_ptr(), sp),
+                  stream, 20, 3)
+    out["rdft_real_input"] = {
+        "workload": "real input: 8192 signals of N=2^12, N(0,1) seed 5, half spectrum out",
+        "ms": round(rms, 5),
+        "GBps": round(rp.info["algo_bytes"] / (rms * 1e-3) / 1e9, 1),
+        "GFLOPs_2.5nlogn": round(rp.info["flops_5nlogn"] / (rms * 1e-3) / 1e9, 1),
+    }
+    rp.close()
     return out
 
 

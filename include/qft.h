@@ -149,6 +149,50 @@ qft_status qft_plan_autotune(qft_plan_t plan, const void* in, void* out, void* s
                              double* ms, int ms_len, int* chosen);
 
 /*
+ * Real-input plans (the rdft, dct and dst functions of Sec. 4.2 and Sec.
+ * 5.2 as entry points of their own).  `batch` real signals of N = 2^log2n
+ * points, 1 <= log2n <= 14 (longer ones: QFT_ERROR_UNSUPPORTED).  Storage:
+ * QFT_C32 = FP32 reals (and complex FP32 outputs), QFT_C16 = FP16 (complex
+ * FP16 outputs), FP32 arithmetic either way.  Two real signals travel
+ * through the transform together, one in each lane of a complex cell, so a
+ * real plan costs about half a complex plan of the same batch.  Such a plan
+ * serves qft_exec_rdft and qft_exec_dct0_dst0 only; the complex exec and
+ * autotune entry points reject it with QFT_ERROR_INVALID_VALUE.
+ * qft_plan_info reports total_points = batch*N, algo_bytes = the rdft's
+ * read + write, flops_5nlogn = 2.5 N log2 N per signal and flops_actual =
+ * 2 N log2 N - 4N + 6 per signal (Table 2, RDFT row).
+ */
+qft_status qft_plan_create_real(qft_plan_t* plan, int log2n, int64_t batch, qft_dtype dtype,
+                                int device);
+
+/*
+ * Real-input DFT (rdft, Sec. 4.2): for each real signal x (row b of `in`,
+ * batch x N reals, at element b*N) the half spectrum
+ *     X(k) = sum_n x(n) exp(-2*pi*i*n*k/N),  k = 0..N/2,
+ * (row b of `out`, batch x (N/2 + 1) complex values, at element b*(N/2+1));
+ * X(N-k) = conj X(k) gives the rest.  Re X(k) is the DCT-0 of the folded
+ * signal c and Im X(k) = -(DST-0 of d).  `in` and `out` must not overlap.
+ */
+qft_status qft_exec_rdft(qft_plan_t plan, const void* in, void* out, void* stream);
+
+/*
+ * DCT-0 and DST-0 of periodization N (dct on s_dc_tt, eq. qft_0B; dst on
+ * s_ds_tt, eq. qft_0C):
+ *     C(k) = c(0) + (-1)^k c(N/2) + sum_{n=1}^{N/2-1} c(n) cos(2*pi*n*k/N),
+ *            k = 0..N/2   (c, C: batch x (N/2 + 1) reals, row b at b*(N/2+1));
+ *     S(k) = sum_{n=1}^{N/2-1} d(n) sin(2*pi*n*k/N),
+ *            k = 1..N/2-1 (d, S: batch x (N/2 - 1) reals, row b at
+ *            b*(N/2-1), d(n) and S(k) at index n-1, k-1).
+ * The real fold of Sec. 4.2 (c(n) = x(n) + x(N-n), d(n) = x(n) - x(N-n))
+ * turns an rdft into exactly these two.  Either pair (c, C) or (d, S) may be
+ * NULL (both members of a pair), not both; for N = 2 the DST-0 is empty and
+ * (d, S) are ignored.  c == C and d == S (in place) are allowed; any other
+ * overlap of the four ranges gives QFT_ERROR_OVERLAP.
+ */
+qft_status qft_exec_dct0_dst0(qft_plan_t plan, const void* c, const void* d, void* C, void* S,
+                              void* stream);
+
+/*
  * Host-only (no GPU needed): writes the FP32 constant table used for
  * transforms up to N = 2^log2n_max into out[0 .. N/4 - 1].  Entry L + m,
  * for L = 1, 2, 4, .., N/8 and 0 <= m < L, is

@@ -9,6 +9,8 @@ gfx950 kernels.
     x = fft_adjoint(X)      # conjugate transpose, unnormalised
     X = QFTFunction.apply(x)            # differentiable (backward = adjoint)
     Y = fft_packed(values, log2n_list)  # uneven batch, one persistent launch
+    H = rdft(xr)            # real input [..., N] -> half spectrum [..., N/2+1]
+    C = dct0(c); S = dst0(d)            # DCT-0 / DST-0 of periodization N
 
 Supported storage: complex64 (FP32) and complex32 / torch.chalf (FP16 storage,
 FP32 arithmetic).  N = 2^r with 1 <= r <= 24.
@@ -16,8 +18,9 @@ FP32 arithmetic).  N = 2^r with 1 <= r <= 24.
 import threading
 
 from . import _lib
-from ._lib import (QFT_C16, QFT_C32, QFT_MAX_LOG2N, QFTError, qft_exec_bwd, qft_exec_fwd,
-                   qft_last_hip_error, qft_plan_autotune, qft_plan_create,
+from ._lib import (QFT_C16, QFT_C32, QFT_MAX_LOG2N, QFTError, qft_exec_bwd,
+                   qft_exec_dct0_dst0, qft_exec_fwd, qft_exec_rdft, qft_last_hip_error,
+                   qft_plan_autotune, qft_plan_create, qft_plan_create_real,
                    qft_plan_create_uneven, qft_plan_destroy, qft_plan_info,
                    qft_plan_schedule_name, qft_plan_schedules, qft_plan_set_schedule,
                    qft_secant_table, qft_status_string)
@@ -27,7 +30,9 @@ __all__ = [
     "qft_plan_create", "qft_plan_create_uneven", "qft_exec_fwd", "qft_exec_bwd",
     "qft_plan_destroy", "qft_plan_info", "qft_secant_table", "qft_status_string",
     "qft_last_hip_error", "qft_plan_schedules", "qft_plan_schedule_name",
-    "qft_plan_set_schedule", "qft_plan_autotune", "QFT_C32", "QFT_C16", "QFT_MAX_LOG2N",
+    "qft_plan_set_schedule", "qft_plan_autotune", "qft_plan_create_real", "qft_exec_rdft",
+    "qft_exec_dct0_dst0", "RealPlan", "rdft", "dct0", "dst0",
+    "QFT_C32", "QFT_C16", "QFT_MAX_LOG2N",
 ]
 
 
@@ -135,8 +140,110 @@ class UnevenPlan(Plan):
         self.info = qft_plan_info(self.handle)
 
 
+def _real_code(t):
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return QFT_C32
+    if t.dtype == torch.float16:
+        return QFT_C16
+    raise TypeError(f"unsupported dtype {t.dtype}; use float32 or float16")
+
+
+class RealPlan:
+    """Real-input plan (qft_plan_create_real): `batch` real signals of 2^log2n
+    points; rdft and DCT-0/DST-0 execs."""
+
+    def __init__(self, log2n, batch, dtype=QFT_C32, device=0):
+        self.log2n, self.batch, self.dtype, self.device = int(log2n), int(batch), dtype, device
+        self.handle = qft_plan_create_real(log2n, batch, dtype, device)
+        self.info = qft_plan_info(self.handle)
+
+    def _rows(self, t, length, what):
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError(f"{what} must be a contiguous GPU tensor")
+        if t.numel() != self.batch * length or _real_code(t) != self.dtype:
+            raise ValueError(f"{what}: expected {self.batch} x {length} reals of the plan's dtype")
+
+    def rdft(self, x, out=None):
+        torch = _torch()
+        N = 1 << self.log2n
+        self._rows(x, N, "x")
+        cdt = torch.complex64 if self.dtype == QFT_C32 else torch.complex32
+        shape = tuple(x.shape[:-1]) + (N // 2 + 1,)
+        out = torch.empty(shape, dtype=cdt, device=x.device) if out is None else out
+        if not (out.is_contiguous() and out.numel() == self.batch * (N // 2 + 1)):
+            raise ValueError("out: expected batch x (N/2 + 1) complex values")
+        qft_exec_rdft(self.handle, x.data_ptr(), out.data_ptr(), _stream_ptr(x.device))
+        return out
+
+    def dct0_dst0(self, c=None, d=None):
+        """(C, S) for the given inputs; a missing input gives None."""
+        torch = _torch()
+        h = (1 << self.log2n) // 2
+        if c is None and d is None:
+            raise ValueError("give c, d or both")
+        if h - 1 == 0:
+            d = None
+        ref = c if c is not None else d
+        C = S = None
+        if c is not None:
+            self._rows(c, h + 1, "c")
+            C = torch.empty_like(c)
+        if d is not None:
+            self._rows(d, h - 1, "d")
+            S = torch.empty_like(d)
+        qft_exec_dct0_dst0(self.handle, c.data_ptr() if c is not None else None,
+                           d.data_ptr() if d is not None else None,
+                           C.data_ptr() if C is not None else None,
+                           S.data_ptr() if S is not None else None, _stream_ptr(ref.device))
+        return C, S
+
+    def close(self):
+        if self.handle:
+            qft_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 _cache = {}
 _cache_lock = threading.Lock()
+
+
+def _real_plan(log2n, rows, t):
+    dev = t.device.index if t.device.index is not None else _torch().cuda.current_device()
+    key = ("real", log2n, rows, _real_code(t), dev)
+    with _cache_lock:
+        p = _cache.get(key)
+        if p is None:
+            p = RealPlan(log2n, rows, key[3], dev)
+            _cache[key] = p
+    return p
+
+
+def rdft(x):
+    """Half spectrum X(k), k = 0..N/2, of the real signals on the last axis."""
+    x = x.contiguous()
+    N = x.shape[-1]
+    return _real_plan(_log2n(N), x.numel() // N, x).rdft(x)
+
+
+def dct0(c):
+    """DCT-0 of periodization N of c(n), n = 0..N/2 (last axis of N/2 + 1)."""
+    c = c.contiguous()
+    N = 2 * (c.shape[-1] - 1)
+    return _real_plan(_log2n(N), c.numel() // c.shape[-1], c).dct0_dst0(c=c)[0]
+
+
+def dst0(d):
+    """DST-0 of periodization N of d(n), n = 1..N/2-1 (last axis of N/2 - 1)."""
+    d = d.contiguous()
+    N = 2 * (d.shape[-1] + 1)
+    return _real_plan(_log2n(N), d.numel() // d.shape[-1], d).dct0_dst0(d=d)[1]
 
 
 def _plan_for(x):

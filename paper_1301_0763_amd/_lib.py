@@ -63,10 +63,14 @@ def lib():
         L.qft_plan_set_schedule.argtypes = [vp, i32]
         L.qft_plan_autotune.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(ctypes.c_double), i32,
                                         ctypes.POINTER(i32)]
+        L.qft_plan_create_real.argtypes = [ctypes.POINTER(vp), i32, i64, i32, i32]
+        L.qft_exec_rdft.argtypes = [vp, vp, vp, vp]
+        L.qft_exec_dct0_dst0.argtypes = [vp, vp, vp, vp, vp, vp]
         for f in ("qft_plan_create", "qft_plan_create_uneven", "qft_exec_fwd", "qft_exec_bwd",
                   "qft_plan_destroy", "qft_plan_info", "qft_secant_table",
                   "qft_last_hip_error", "qft_plan_schedules", "qft_plan_set_schedule",
-                  "qft_plan_autotune"):
+                  "qft_plan_autotune", "qft_plan_create_real", "qft_exec_rdft",
+                  "qft_exec_dct0_dst0"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -157,3 +161,21 @@ def qft_plan_autotune(plan, in_ptr, out_ptr, stream=0, reps=10):
     _check(lib().qft_plan_autotune(plan, in_ptr, out_ptr, stream, int(reps), ms, n,
                                    ctypes.byref(chosen)), "qft_plan_autotune")
     return chosen.value, [ms[i] for i in range(n)]
+
+
+def qft_plan_create_real(log2n, batch, dtype=QFT_C32, device=0):
+    """Real-input plan for `batch` real signals of 2^log2n points."""
+    h = ctypes.c_void_p()
+    _check(lib().qft_plan_create_real(ctypes.byref(h), int(log2n), int(batch), int(dtype),
+                                      int(device)), "qft_plan_create_real")
+    return h.value
+
+
+def qft_exec_rdft(plan, in_ptr, out_ptr, stream=0):
+    _check(lib().qft_exec_rdft(plan, in_ptr, out_ptr, stream), "qft_exec_rdft")
+
+
+def qft_exec_dct0_dst0(plan, c_ptr, d_ptr, C_ptr, S_ptr, stream=0):
+    """Null (None/0) pointers leave out the DCT-0 or the DST-0."""
+    _check(lib().qft_exec_dct0_dst0(plan, c_ptr or None, d_ptr or None, C_ptr or None,
+                                    S_ptr or None, stream), "qft_exec_dct0_dst0")

@@ -85,6 +85,19 @@ template <> struct Store<1> {
   static QFT_HD void st(T* p, int64_t i, float2 v) { p[i] = __float22half2_rn(v); }
 };
 
+// Real element storage (real-input entry points): FP32 or FP16.
+template <int DT> struct RStore;
+template <> struct RStore<0> {
+  using T = float;
+  static QFT_HD float ld(const T* p, int64_t i) { return p[i]; }
+  static QFT_HD void st(T* p, int64_t i, float v) { p[i] = v; }
+};
+template <> struct RStore<1> {
+  using T = __half;
+  static QFT_HD float ld(const T* p, int64_t i) { return __half2float(p[i]); }
+  static QFT_HD void st(T* p, int64_t i, float v) { p[i] = __float2half_rn(v); }
+};
+
 template <bool SWAP> QFT_HD float2 sw(float2 v) {
   if constexpr (SWAP) return make_float2(v.y, v.x);
   else return v;
@@ -1525,37 +1538,191 @@ QFT_HD void chain_base_dst(SP sd) {
   }
 }
 
-// Global input/output of the transforms of a tile.  SWAP loads and stores
-// every value with its real and imaginary parts exchanged, which turns the
-// forward transform into the adjoint: F^H g = swap(F swap(g)).  Transform t
-// of the tile starts at element x + base + t 2^LOGN (ContigIO, a contiguous
-// batch) or at x + offs[t] (GatherIO, an uneven batch's offset list).
+// Global input and output of the transforms of a tile.  A tile body asks its
+// IO for two things:
+//  * fetch(t, m, r) / fold(r, m, lo, hi): the samples of position m of
+//    transform t (0 <= m < N/2) and the two heap values they give: for
+//    m >= 1 the DCT-side cell c(m) and the DST-side cell d(m) of the real fold
+//    (Sec. 4.2), for m = 0 the cells c(0) and c(N/2);
+//  * put(o, n, k, C, S) for 0 < k < N/2 and put_edge(o, k, C) for k = 0, N/2:
+//    the outputs from the DCT-0 result C(k) and the DST-0 result S(k).
+// Every cell carries two real signals (the float2 lanes).
+//
+// ContigIO / GatherIO: complex transforms, lane x = Re, lane y = Im (cdft,
+// Sec. 4.1): X(k) = C(k) - i S(k) per real signal, combined into
+// X(k), X(N-k).  SWAP exchanges real and imaginary parts on every load and
+// store, which turns the forward transform into the adjoint:
+// F^H g = swap(F swap(g)).  Transform t starts at x + t 2^LOGN (contiguous
+// batch) or at x + offs[t] (an uneven batch's offset list).
 template <int DT, bool SWAP>
-struct SwapIO {
+struct ComplexIO {
   using E = typename Store<DT>::T;
+  struct Raw {
+    float2 a, b;
+  };
   QFT_HD static float2 load(const E* p, int i) { return sw<SWAP>(Store<DT>::ld(p, i)); }
   QFT_HD static void store(E* p, int i, float2 v) { Store<DT>::st(p, i, sw<SWAP>(v)); }
+  QFT_HD static void fold(const Raw& r, int m, float2& lo, float2& hi) {
+    if (m == 0) {
+      lo = r.a;
+      hi = r.b;
+    } else {
+      lo = cadd(r.a, r.b);
+      hi = csub(r.a, r.b);
+    }
+  }
+  QFT_HD static void put(E* Xt, int n, int k, float2 C, float2 S) {
+    store(Xt, k, make_float2(C.x + S.y, C.y - S.x));
+    store(Xt, n - k, make_float2(C.x - S.y, C.y + S.x));
+  }
+  QFT_HD static void put_edge(E* Xt, int k, float2 C) { store(Xt, k, C); }
 };
 
 template <int DT, bool SWAP, int LOGN>
-struct ContigIO : SwapIO<DT, SWAP> {
+struct ContigIO : ComplexIO<DT, SWAP> {
   using E = typename Store<DT>::T;
+  using typename ComplexIO<DT, SWAP>::Raw;
   const E* x;
   E* X;
   QFT_HD ContigIO(const E* x_, E* X_) : x(x_), X(X_) {}
-  QFT_HD const E* src(int t) const { return x + ((int64_t)t << LOGN); }
-  QFT_HD E* dst(int t) const { return X + ((int64_t)t << LOGN); }
+  QFT_HD E* out(int t) const { return X + ((int64_t)t << LOGN); }
+  QFT_HD void fetch(int t, int m, Raw& r) const {
+    constexpr int n = 1 << LOGN, h = n >> 1;
+    const E* xt = x + ((int64_t)t << LOGN);
+    r.a = this->load(xt, m);
+    r.b = this->load(xt, m == 0 ? h : n - m);
+  }
 };
 
 template <int DT, bool SWAP>
-struct GatherIO : SwapIO<DT, SWAP> {
+struct GatherIO : ComplexIO<DT, SWAP> {
   using E = typename Store<DT>::T;
+  using typename ComplexIO<DT, SWAP>::Raw;
   const E* x;
   E* X;
   const int64_t* offs;
-  QFT_HD GatherIO(const E* x_, E* X_, const int64_t* o) : x(x_), X(X_), offs(o) {}
-  QFT_HD const E* src(int t) const { return x + offs[t]; }
-  QFT_HD E* dst(int t) const { return X + offs[t]; }
+  int logn;
+  QFT_HD GatherIO(const E* x_, E* X_, const int64_t* o, int lg)
+      : x(x_), X(X_), offs(o), logn(lg) {}
+  QFT_HD E* out(int t) const { return X + offs[t]; }
+  QFT_HD void fetch(int t, int m, Raw& r) const {
+    const int n = 1 << logn, h = n >> 1;
+    const E* xt = x + offs[t];
+    r.a = this->load(xt, m);
+    r.b = this->load(xt, m == 0 ? h : n - m);
+  }
+};
+
+// Real-input transform (rdft, Sec. 4.2) of real signals 2t and 2t+1 of a
+// batch of `rows` signals of N = 2^LOGN points (row r at x + r N), as the
+// two lanes of transform t.  Output: the half spectrum X(k) = C(k) - i S(k),
+// k = 0..N/2, of each signal (row r at X + r (N/2 + 1)).  Signal 2t+1 past
+// the batch reads as zero and is not written.
+template <int DT, int LOGN>
+struct RealPairIO {
+  using R = typename RStore<DT>::T;
+  using E = typename Store<DT>::T;
+  static constexpr int n = 1 << LOGN, h = n >> 1;
+  struct Raw {
+    float2 a, b;
+  };
+  struct Out {
+    E* A;
+    E* B;
+  };
+  const R* x;
+  E* X;
+  int64_t rows;
+  QFT_HD bool has_b(int t) const { return 2 * (int64_t)t + 1 < rows; }
+  QFT_HD float2 pair(int t, int i) const {
+    const int64_t r0 = 2 * (int64_t)t;
+    const float va = RStore<DT>::ld(x, r0 * n + i);
+    const float vb = has_b(t) ? RStore<DT>::ld(x, (r0 + 1) * n + i) : 0.f;
+    return make_float2(va, vb);
+  }
+  QFT_HD void fetch(int t, int m, Raw& r) const {
+    r.a = pair(t, m);
+    r.b = pair(t, m == 0 ? h : n - m);
+  }
+  QFT_HD static void fold(const Raw& r, int m, float2& lo, float2& hi) {
+    ComplexIO<DT, false>::fold(typename ComplexIO<DT, false>::Raw{r.a, r.b}, m, lo, hi);
+  }
+  QFT_HD Out out(int t) const {
+    const int64_t r0 = 2 * (int64_t)t;
+    return Out{X + r0 * (h + 1), has_b(t) ? X + (r0 + 1) * (h + 1) : nullptr};
+  }
+  QFT_HD static void put(const Out& o, int, int k, float2 C, float2 S) {
+    Store<DT>::st(o.A, k, make_float2(C.x, -S.x));
+    if (o.B) Store<DT>::st(o.B, k, make_float2(C.y, -S.y));
+  }
+  QFT_HD static void put_edge(const Out& o, int k, float2 C) {
+    Store<DT>::st(o.A, k, make_float2(C.x, 0.f));
+    if (o.B) Store<DT>::st(o.B, k, make_float2(C.y, 0.f));
+  }
+};
+
+// Standalone DCT-0 and DST-0 of periodization N = 2^LOGN (``dct`` on
+// s_dc_tt, eq. qft_0B; ``dst`` on s_ds_tt, eq. qft_0C): inputs c(n),
+// n = 0..N/2 (row r at c + r (N/2+1)) and d(n), n = 1..N/2-1 (row r at
+// d + r (N/2-1), d(n) at index n-1); outputs C(k), k = 0..N/2 and S(k),
+// k = 1..N/2-1 in the same layouts.  Signals 2t and 2t+1 are the lanes of
+// transform t.  A null input pair (c and C, or d and S) reads as zero and is
+// not written.
+template <int DT, int LOGN>
+struct DctDstIO {
+  using R = typename RStore<DT>::T;
+  static constexpr int n = 1 << LOGN, h = n >> 1;
+  struct Raw {
+    float2 a, b;
+  };
+  struct Out {
+    R* CA;
+    R* CB;
+    R* SA;
+    R* SB;
+  };
+  const R* c;
+  const R* d;
+  R* C;
+  R* S;
+  int64_t rows;
+  QFT_HD bool has_b(int t) const { return 2 * (int64_t)t + 1 < rows; }
+  QFT_HD float2 pair(const R* p, int len, int t, int i) const {
+    if (!p) return make_float2(0.f, 0.f);
+    const int64_t r0 = 2 * (int64_t)t;
+    const float va = RStore<DT>::ld(p, r0 * len + i);
+    const float vb = has_b(t) ? RStore<DT>::ld(p, (r0 + 1) * len + i) : 0.f;
+    return make_float2(va, vb);
+  }
+  QFT_HD void fetch(int t, int m, Raw& r) const {
+    if (m == 0) {
+      r.a = pair(c, h + 1, t, 0);
+      r.b = pair(c, h + 1, t, h);
+    } else {
+      r.a = pair(c, h + 1, t, m);
+      r.b = pair(d, h - 1, t, m - 1);
+    }
+  }
+  QFT_HD static void fold(const Raw& r, int, float2& lo, float2& hi) {
+    lo = r.a;
+    hi = r.b;
+  }
+  QFT_HD Out out(int t) const {
+    const int64_t r0 = 2 * (int64_t)t;
+    const bool b = has_b(t);
+    return Out{C ? C + r0 * (h + 1) : nullptr, (C && b) ? C + (r0 + 1) * (h + 1) : nullptr,
+               S ? S + r0 * (h - 1) : nullptr, (S && b) ? S + (r0 + 1) * (h - 1) : nullptr};
+  }
+  QFT_HD static void put(const Out& o, int, int k, float2 Cv, float2 Sv) {
+    if (o.CA) RStore<DT>::st(o.CA, k, Cv.x);
+    if (o.CB) RStore<DT>::st(o.CB, k, Cv.y);
+    if (o.SA) RStore<DT>::st(o.SA, k - 1, Sv.x);
+    if (o.SB) RStore<DT>::st(o.SB, k - 1, Sv.y);
+  }
+  QFT_HD static void put_edge(const Out& o, int k, float2 Cv) {
+    if (o.CA) RStore<DT>::st(o.CA, k, Cv.x);
+    if (o.CB) RStore<DT>::st(o.CB, k, Cv.y);
+  }
 };
 
 struct NoIO {};
@@ -1603,12 +1770,6 @@ QFT_HD constexpr int chain_first_block_pass(int pl, int pend, int tpw, int lanes
              : chain_first_block_pass(pl + 3, pend, tpw, lanes);
 }
 
-template <class IO, typename EP>
-QFT_HD void combine_put(const IO& io, EP Xt, int n, int k, float2 C, float2 S) {
-  io.store(Xt, k, make_float2(C.x + S.y, C.y - S.x));
-  io.store(Xt, n - k, make_float2(C.x - S.y, C.y + S.x));
-}
-
 // Last pass (levels PLOG-2 .. PLOG) fused with the cdft combine of Sec. 4.1:
 // the DCT and the DST group of one index hold C and S at the same indices.
 template <int PLOG, int T, int NT, class Acc, class IO>
@@ -1622,7 +1783,7 @@ QFT_HD void chain_top_combine(const Acc& acc, const IO& io, int Tact, int tid) {
     if (i < total) {
       const int t = i / G, g = i - t * G;
       if (t < Tact) {
-        const auto Xt = io.dst(t);
+        const auto Xt = io.out(t);
         float2 vc[S], vs[S];
         if (g == 0) {
           chain_special_load<P, K, false>(acc.dc(t), acc.top(t), vc);
@@ -1631,15 +1792,15 @@ QFT_HD void chain_top_combine(const Acc& acc, const IO& io, int Tact, int tid) {
           constexpr ChainPairing pr = chain_pairing(P, K);
 #pragma unroll
           for (int m = 0; m < fin.n; ++m) {
-            if (pr.ms[m] < 0) io.store(Xt, fin.idx[m], vc[m]);  // X(0), X(N/2)
-            else combine_put(io, Xt, N, fin.idx[m], vc[m], vs[pr.ms[m]]);
+            if (pr.ms[m] < 0) io.put_edge(Xt, fin.idx[m], vc[m]);  // k = 0, N/2
+            else io.put(Xt, N, fin.idx[m], vc[m], vs[pr.ms[m]]);
           }
         } else {
           chain_generic<P, K, false>(acc.dc(t), g, vc);
           chain_generic<P, K, true>(acc.ds(t), g, vs);
 #pragma unroll
           for (int m = 0; m < (1 << K); ++m)
-            combine_put(io, Xt, N, chain_c(P, K, m) + chain_sgn(K, m) * g, vc[m], vs[m]);
+            io.put(Xt, N, chain_c(P, K, m) + chain_sgn(K, m) * g, vc[m], vs[m]);
         }
       }
     }
@@ -1689,17 +1850,11 @@ QFT_HD void tile_body_s(const IO& io, WP W, int Tact, const float* sec, int tid,
   constexpr int total = T << (LOGN - 1);
   constexpr int FI = (total + NT - 1) / NT;
   const int tot_act = Tact << (LOGN - 1);
-  float2 av[FI], bv[FI];
+  typename IO::Raw raw[FI];
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
     const int i = tid + it * NT;
-    if (i < tot_act) {
-      const int t = i >> (LOGN - 1);
-      const int m = i & (h - 1);
-      const auto xt = io.src(t);
-      av[it] = io.load(xt, m);
-      bv[it] = io.load(xt, m == 0 ? h : n - m);
-    }
+    if (i < tot_act) io.fetch(i >> (LOGN - 1), i & (h - 1), raw[it]);
   }
 #pragma unroll
   for (int it = 0; it < FI; ++it) {
@@ -1708,15 +1863,16 @@ QFT_HD void tile_body_s(const IO& io, WP W, int Tact, const float* sec, int tid,
       const int t = i >> (LOGN - 1);
       const int m = i & (h - 1);
       auto w = W + (t << LOGN);
-      const float2 a = av[it], b = bv[it];
+      float2 lo, hi;
+      io.fold(raw[it], m, lo, hi);
       if (m == 0) {
-        w[0] = a;
-        w[h] = b;
+        w[0] = lo;  // c(0)
+        w[h] = hi;  // c(N/2)
       } else {
         const int l = __builtin_ctz(m);
         const int cell = (n >> (l + 2)) + (m >> (l + 1));
-        w[cell] = cadd(a, b);
-        w[h + cell] = csub(a, b);
+        w[cell] = lo;
+        w[h + cell] = hi;
       }
     }
   }
@@ -1734,13 +1890,13 @@ QFT_HD void tile_body_s(const IO& io, WP W, int Tact, const float* sec, int tid,
     if (i < tot_act) {
       const int t = i >> (LOGN - 1);
       const int k = i & (h - 1);
-      const auto Xt = io.dst(t);
+      const auto Xt = io.out(t);
       auto w = W + (t << LOGN);
       if (k == 0) {
-        io.store(Xt, 0, w[0]);
-        io.store(Xt, h, w[h]);
+        io.put_edge(Xt, 0, w[0]);
+        io.put_edge(Xt, h, w[h]);
       } else {
-        combine_put(io, Xt, n, k, w[k], w[h + k]);
+        io.put(Xt, n, k, w[k], w[h + k]);
       }
     }
   }
@@ -1888,59 +2044,61 @@ struct HeadSides {  // the head segments of pass A: DCT, DST and the top cell
   QFT_HD LP top(int) const { return L + 2 * mc; }
 };
 
-template <int DT, bool SWAP, int MC_LOG2, int NT, int WAVE, class Sync, class WSync,
-          typename GP, typename LP>
-QFT_HD void tp_pass_a2(const typename Store<DT>::T* xt, GP wt, LP L, int j, const float* sec,
-                       int tid, Sync sync, WSync wsync) {
+// Folded heap values of position q of segment j < 2 (both sides) straight
+// from x: c(n) = x(n) + x(N-n), d(n) = x(n) - x(N-n) with the n of heap cell
+// p = j MC + q (heap_fold_value); cell 0 holds c(0) (its DST cell is unused).
+template <int DT, bool SWAP, int MC_LOG2>
+QFT_HD void tp_gather01(const typename Store<DT>::T* xt, int j, int q, float2& vc, float2& vs) {
+  constexpr int MC = 1 << MC_LOG2;
+  constexpr int logn = MC_LOG2 + 3;
+  constexpr int N = 1 << logn;
+  const int p = j * MC + q;
+  if (p == 0) {
+    vc = sw<SWAP>(Store<DT>::ld(xt, 0));  // c(0)
+    vs = make_float2(0.f, 0.f);
+  } else {
+    const int lgM = 31 - __builtin_clz(p);
+    const int v = p - (1 << lgM);
+    const int n = (2 * v + 1) << (logn - 2 - lgM);
+    const float2 a = sw<SWAP>(Store<DT>::ld(xt, n));
+    const float2 b = sw<SWAP>(Store<DT>::ld(xt, N - n));
+    vc = cadd(a, b);
+    vs = csub(a, b);
+  }
+}
+
+// Segments 2 and 3 (the halves of the block N/4 after its top forward round,
+// S = 2 MC: pair (q, 2MC-1-q), i.e. odd n = 2q+1 and its mirror N/2 - n) at
+// position q, both from the same four samples of x.
+template <int DT, bool SWAP, int MC_LOG2>
+QFT_HD void tp_gather23(const typename Store<DT>::T* xt, int q, const float* __restrict__ sec,
+                        float2& vc2, float2& vs2, float2& vc3, float2& vs3) {
   constexpr int MC = 1 << MC_LOG2;
   constexpr int logn = MC_LOG2 + 3;
   constexpr int N = 1 << logn, h = N >> 1;
-  constexpr int NI = MC / NT;  // positions per thread
-  float2 vc[NI], vs[NI];
-#pragma unroll
-  for (int it = 0; it < NI; ++it) {
-    const int q = tid + it * NT;
-    const int p = j * MC + q;
-    if (j < 2) {
-      if (p == 0) {
-        vc[it] = sw<SWAP>(Store<DT>::ld(xt, 0));  // c(0)
-        vs[it] = make_float2(0.f, 0.f);           // (DST cell 0 holds the top)
-      } else {
-        const int lgM = 31 - __builtin_clz(p);
-        const int v = p - (1 << lgM);
-        const int n = (2 * v + 1) << (logn - 2 - lgM);
-        const float2 a = sw<SWAP>(Store<DT>::ld(xt, n));
-        const float2 b = sw<SWAP>(Store<DT>::ld(xt, N - n));
-        vc[it] = cadd(a, b);
-        vs[it] = csub(a, b);
-      }
-    } else {
-      const int n = 2 * q + 1;
-      const float2 a0 = sw<SWAP>(Store<DT>::ld(xt, n));
-      const float2 b0 = sw<SWAP>(Store<DT>::ld(xt, N - n));
-      const float2 a1 = sw<SWAP>(Store<DT>::ld(xt, h - n));
-      const float2 b1 = sw<SWAP>(Store<DT>::ld(xt, h + n));
-      const float2 c0 = cadd(a0, b0), c1 = cadd(a1, b1);  // c(n), c(N/2-n)
-      const float2 d0 = csub(a0, b0), d1 = csub(a1, b1);  // d(n), d(N/2-n)
-      if (j == 2) {
-        vc[it] = cadd(c0, c1);
-        vs[it] = csub(d0, d1);
-      } else {
-        const float hs = sec[MC + q];
-        vc[it] = cscale(csub(c0, c1), hs);
-        vs[it] = cscale(cadd(d0, d1), hs);
-      }
-    }
-  }
-  float2 topv = make_float2(0.f, 0.f);
-  if (j == 0 && tid == 0) topv = sw<SWAP>(Store<DT>::ld(xt, h));  // c(N/2)
-#pragma unroll
-  for (int it = 0; it < NI; ++it) {
-    const int q = tid + it * NT;
-    L[q] = vc[it];
-    L[MC + q] = vs[it];
-  }
-  if (j == 0 && tid == 0) L[2 * MC] = topv;
+  const int n = 2 * q + 1;
+  const float2 a0 = sw<SWAP>(Store<DT>::ld(xt, n));
+  const float2 b0 = sw<SWAP>(Store<DT>::ld(xt, N - n));
+  const float2 a1 = sw<SWAP>(Store<DT>::ld(xt, h - n));
+  const float2 b1 = sw<SWAP>(Store<DT>::ld(xt, h + n));
+  const float2 c0 = cadd(a0, b0), c1 = cadd(a1, b1);  // c(n), c(N/2-n)
+  const float2 d0 = csub(a0, b0), d1 = csub(a1, b1);  // d(n), d(N/2-n)
+  const float hs = sec[MC + q];
+  vc2 = cadd(c0, c1);
+  vs2 = csub(d0, d1);
+  vc3 = cscale(csub(c0, c1), hs);
+  vs3 = cscale(cadd(d0, d1), hs);
+}
+
+// Segment j of pass A once its cells are in LDS (DCT at L[0, MC), DST at
+// L[MC, 2MC), the top cell at L[2MC]): the remaining rounds, for the head the
+// DCT-0/DST-0 chain up to P = 2 MC, and the copy to the heap buffer.  Starts
+// with a barrier (the caller's LDS stores) and leaves LDS being read.
+template <int MC_LOG2, int NT, int WAVE, class Sync, class WSync, typename GP, typename LP>
+QFT_HD void tp_segment(GP wt, LP L, int j, const float* sec, int tid, Sync sync, WSync wsync) {
+  constexpr int MC = 1 << MC_LOG2;
+  constexpr int h = 4 * MC;
+  constexpr int NI = MC / NT;
   sync();
   if (j == 0) {
     sweeps_s<MC_LOG2 - 1, MC_LOG2, 2, NT, SIDES_ALT, true>(L, sec, tid, sync);
@@ -1961,6 +2119,41 @@ QFT_HD void tp_pass_a2(const typename Store<DT>::T* xt, GP wt, LP L, int j, cons
     if (!(j == 0 && q == 0)) wt[h + j * MC + q] = (float2)L[MC + q];
   }
   if (j == 0 && tid == 0) wt[h] = (float2)L[2 * MC];  // D_{2MC}(MC): top cell
+}
+
+// Pass A with both sides of one segment index j in the same workgroup: the
+// DCT and DST cells of a position come from the same x samples (c = a + b,
+// d = a - b), so x is gathered once for both.
+template <int DT, bool SWAP, int MC_LOG2, int NT, int WAVE, class Sync, class WSync,
+          typename GP, typename LP>
+QFT_HD void tp_pass_a2(const typename Store<DT>::T* xt, GP wt, LP L, int j, const float* sec,
+                       int tid, Sync sync, WSync wsync) {
+  constexpr int MC = 1 << MC_LOG2;
+  constexpr int h = 4 * MC;
+  constexpr int NI = MC / NT;  // positions per thread
+  float2 vc[NI], vs[NI];
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int q = tid + it * NT;
+    if (j < 2) {
+      tp_gather01<DT, SWAP, MC_LOG2>(xt, j, q, vc[it], vs[it]);
+    } else {
+      float2 c2, s2, c3, s3;
+      tp_gather23<DT, SWAP, MC_LOG2>(xt, q, sec, c2, s2, c3, s3);
+      vc[it] = j == 2 ? c2 : c3;
+      vs[it] = j == 2 ? s2 : s3;
+    }
+  }
+  float2 topv = make_float2(0.f, 0.f);
+  if (j == 0 && tid == 0) topv = sw<SWAP>(Store<DT>::ld(xt, h));  // c(N/2)
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int q = tid + it * NT;
+    L[q] = vc[it];
+    L[MC + q] = vs[it];
+  }
+  if (j == 0 && tid == 0) L[2 * MC] = topv;
+  tp_segment<MC_LOG2, NT, WAVE>(wt, L, j, sec, tid, sync, wsync);
 }
 
 }  // namespace qftk

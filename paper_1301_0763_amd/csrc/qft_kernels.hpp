@@ -51,6 +51,16 @@ struct TileGroup {
   int64_t* d_offs;
   int ulog2n;
   int64_t ubatch;
+  int64_t rows;  // real-input plans: real signals (2 per transform slot)
+};
+
+// Pointers of a real-input exec: rdft in0 -> out0; DCT-0/DST-0 in0 (c) ->
+// out0 (C) and in1 (d) -> out1 (S), either pair may be null.
+struct RealArgs {
+  const void* in0;
+  const void* in1;
+  void* out0;
+  void* out1;
 };
 
 // Launches one group with the tile kernels of storage type DT (0: complex
@@ -60,5 +70,11 @@ struct TileGroup {
 template <int DT, int TL, bool SWAP>
 hipError_t launch_tiles(const TileGroup& g, const void* in, void* out, const float* sec,
                         hipStream_t st);
+
+// Launches a uniform group of a real-input plan: kind 0 = rdft, 1 = DCT-0 /
+// DST-0 (qft_tiles.hip, instantiated in the forward translation units).
+template <int DT, int TL>
+hipError_t launch_real(const TileGroup& g, int kind, const RealArgs& a, const float* sec,
+                       hipStream_t st);
 
 }  // namespace qftk

@@ -149,6 +149,8 @@ struct qft_plan_s {
   int device = 0;
   qft_dtype dtype = QFT_C32;
   bool uneven = false;
+  bool real = false;          // real-input plan (rdft, DCT-0/DST-0)
+  int64_t real_algo_bytes = 0;
   int log2n = 0;        // uniform plans
   int64_t batch = 0;    // uniform plans
   int64_t total_points = 0;
@@ -251,7 +253,7 @@ qft_status uniform_group(const qft_plan_s* p, int tl, qftk::TileGroup* g) {
   const int64_t per = (int64_t)1 << (tl - p->log2n);
   const int64_t ntiles = (p->batch + per - 1) / per;
   if (ntiles > 0x7fffffff) return QFT_ERROR_INVALID_VALUE;
-  *g = qftk::TileGroup{tl, (int)ntiles, (int)ntiles, nullptr, nullptr, p->log2n, p->batch};
+  *g = qftk::TileGroup{tl, (int)ntiles, (int)ntiles, nullptr, nullptr, p->log2n, p->batch, 0};
   return QFT_SUCCESS;
 }
 
@@ -262,7 +264,7 @@ qft_status uneven_group(qft_plan_s* p, const int32_t* log2n, const std::vector<i
   std::vector<int64_t> perm;
   qftk::build_tiles(log2n, offsets, lo, hi, tl, desc, perm);
   *g = qftk::TileGroup{tl, (int)desc.size(), group_grid(p, tl, (int64_t)desc.size(), true),
-                       nullptr, nullptr, 0, 0};
+                       nullptr, nullptr, 0, 0, 0};
   if (desc.empty()) return QFT_SUCCESS;
   std::vector<int4> tiles;
   for (const qftk::TileDesc& d : desc) tiles.push_back(make_int4(d.log2n, d.first, d.count, 0));
@@ -425,11 +427,35 @@ qft_status exec_sched(const qft_plan_s* plan, int sched, const void* in, void* o
 
 template <bool SWAP>
 qft_status exec_impl(qft_plan_t plan, const void* in, void* out, void* stream) {
+  if (plan && plan->real) return QFT_ERROR_INVALID_VALUE;
   const qft_status c = check_buffers(plan, in, out);
   if (c != QFT_SUCCESS) return c;
   DeviceGuard guard(plan->device);
   if (!guard.ok) return hip_fail(hipErrorInvalidDevice);
   return exec_sched<SWAP>(plan, plan->chosen, in, out, (hipStream_t)stream);
+}
+
+// Byte range [p, p + n) of a real-input exec argument; null pointers are empty.
+struct Span {
+  uintptr_t a = 0, b = 0;
+  Span(const void* p, int64_t n) : a((uintptr_t)p), b(p ? (uintptr_t)p + (uintptr_t)n : 0) {}
+  bool overlaps(const Span& o) const { return a && o.a && a < o.b && o.a < b; }
+};
+
+qft_status run_real(const qft_plan_s* p, int kind, const qftk::RealArgs& a, hipStream_t st) {
+  const qftk::TileGroup& g = p->schedules[p->chosen].groups[0];
+  hipError_t e = hipErrorInvalidValue;
+  const bool h16 = p->dtype == QFT_C16;
+  switch (g.tl) {
+    case 12: e = h16 ? qftk::launch_real<1, 12>(g, kind, a, p->d_sec, st)
+                     : qftk::launch_real<0, 12>(g, kind, a, p->d_sec, st); break;
+    case 13: e = h16 ? qftk::launch_real<1, 13>(g, kind, a, p->d_sec, st)
+                     : qftk::launch_real<0, 13>(g, kind, a, p->d_sec, st); break;
+    case 14: e = h16 ? qftk::launch_real<1, 14>(g, kind, a, p->d_sec, st)
+                     : qftk::launch_real<0, 14>(g, kind, a, p->d_sec, st); break;
+    default: break;
+  }
+  return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
 }
 
 qft_plan_s* new_plan(int device, qft_dtype dtype, int cus) {
@@ -630,7 +656,7 @@ qft_status qft_plan_info(qft_plan_t plan, int64_t* total_points, int64_t* algo_b
   if (!plan) return QFT_ERROR_INVALID_VALUE;
   const int64_t esz = plan->dtype == QFT_C32 ? 8 : 4;
   if (total_points) *total_points = plan->total_points;
-  if (algo_bytes) *algo_bytes = 2 * plan->total_points * esz;
+  if (algo_bytes) *algo_bytes = plan->real ? plan->real_algo_bytes : 2 * plan->total_points * esz;
   if (flops_5nlogn) *flops_5nlogn = plan->flops_5nlogn;
   if (flops_actual) *flops_actual = plan->flops_actual;
   return QFT_SUCCESS;
@@ -657,6 +683,7 @@ qft_status qft_plan_set_schedule(qft_plan_t plan, int schedule) {
 
 qft_status qft_plan_autotune(qft_plan_t plan, const void* in, void* out, void* stream, int reps,
                              double* ms, int ms_len, int* chosen) {
+  if (plan && plan->real) return QFT_ERROR_INVALID_VALUE;
   qft_status c = check_buffers(plan, in, out);
   if (c != QFT_SUCCESS) return c;
   if (reps < 1 || reps > 10000 || ms_len < 0 || (ms_len > 0 && !ms))
@@ -698,6 +725,86 @@ qft_status qft_plan_autotune(qft_plan_t plan, const void* in, void* out, void* s
   plan->chosen = best;
   if (chosen) *chosen = best;
   return QFT_SUCCESS;
+}
+
+qft_status qft_plan_create_real(qft_plan_t* plan, int log2n, int64_t batch, qft_dtype dtype,
+                                int device) {
+  if (!plan) return QFT_ERROR_INVALID_VALUE;
+  *plan = nullptr;
+  if (batch <= 0 || (dtype != QFT_C32 && dtype != QFT_C16)) return QFT_ERROR_INVALID_VALUE;
+  if (log2n < 1 || log2n > QFT_MAX_LOG2N) return QFT_ERROR_INVALID_SIZE;
+  if (log2n > qftk::kMaxTileLog2) return QFT_ERROR_UNSUPPORTED;
+  if (batch > ((int64_t)1 << 40) >> log2n) return QFT_ERROR_INVALID_VALUE;
+  int cus = 0;
+  qft_status s = check_device(device, &cus);
+  if (s != QFT_SUCCESS) return s;
+  DeviceGuard guard(device);
+  if (!guard.ok) return hip_fail(hipErrorInvalidDevice);
+  qft_plan_s* p = new_plan(device, dtype, cus);
+  if (!p) return QFT_ERROR_ALLOC;
+  p->real = true;
+  p->log2n = log2n;
+  p->batch = batch;
+  p->max_log2n = log2n;
+  const int64_t N = (int64_t)1 << log2n;
+  const int64_t rsz = dtype == QFT_C32 ? 4 : 2;
+  p->total_points = batch * N;
+  p->flops_5nlogn = 2.5 * (double)N * log2n * (double)batch;
+  // Table 2, RDFT row: (N log N - 3N)/2 + 2 multiplications, (3 N log N - 5N)/2 + 4 additions
+  p->flops_actual = (2.0 * (double)N * log2n - 4.0 * (double)N + 6.0) * (double)batch;
+  p->real_algo_bytes = batch * (N * rsz + (N / 2 + 1) * 2 * rsz);
+  const int tl = std::max(qftk::kMinTileLog2, log2n);
+  const int64_t slots = (batch + 1) / 2, per = (int64_t)1 << (tl - log2n);
+  const int64_t ntiles = (slots + per - 1) / per;
+  if (ntiles > 0x7fffffff) {
+    free_plan(p);
+    return QFT_ERROR_INVALID_VALUE;
+  }
+  Schedule sc;
+  sc.name = "t" + std::to_string(tl) + ":" + std::to_string(log2n) + "/real";
+  sc.groups.push_back(qftk::TileGroup{tl, (int)ntiles, (int)ntiles, nullptr, nullptr, log2n, slots,
+                                      batch});
+  p->schedules.push_back(sc);
+  s = alloc_common(p);
+  if (s != QFT_SUCCESS) {
+    free_plan(p);
+    return s;
+  }
+  *plan = p;
+  return QFT_SUCCESS;
+}
+
+qft_status qft_exec_rdft(qft_plan_t plan, const void* in, void* out, void* stream) {
+  if (!plan || !plan->real || !in || !out) return QFT_ERROR_INVALID_VALUE;
+  const int64_t rsz = plan->dtype == QFT_C32 ? 4 : 2;
+  if (((uintptr_t)in % rsz) != 0 || ((uintptr_t)out % (2 * rsz)) != 0) return QFT_ERROR_ALIGNMENT;
+  const int64_t N = (int64_t)1 << plan->log2n;
+  if (Span(in, plan->batch * N * rsz).overlaps(Span(out, plan->batch * (N / 2 + 1) * 2 * rsz)))
+    return QFT_ERROR_OVERLAP;
+  DeviceGuard guard(plan->device);
+  if (!guard.ok) return hip_fail(hipErrorInvalidDevice);
+  return run_real(plan, 0, qftk::RealArgs{in, nullptr, out, nullptr}, (hipStream_t)stream);
+}
+
+qft_status qft_exec_dct0_dst0(qft_plan_t plan, const void* c, const void* d, void* C, void* S,
+                              void* stream) {
+  if (!plan || !plan->real) return QFT_ERROR_INVALID_VALUE;
+  const int64_t N = (int64_t)1 << plan->log2n, h = N / 2;
+  if (h - 1 == 0) d = S = nullptr;  // N = 2: the DST-0 has no points
+  if ((c == nullptr) != (C == nullptr) || (d == nullptr) != (S == nullptr) || (!c && !d))
+    return QFT_ERROR_INVALID_VALUE;
+  const int64_t rsz = plan->dtype == QFT_C32 ? 4 : 2;
+  for (const void* q : {(const void*)c, (const void*)d, (const void*)C, (const void*)S})
+    if (((uintptr_t)q % rsz) != 0) return QFT_ERROR_ALIGNMENT;
+  const Span sc(c, plan->batch * (h + 1) * rsz), sd(d, plan->batch * (h - 1) * rsz);
+  const Span sC(C, plan->batch * (h + 1) * rsz), sS(S, plan->batch * (h - 1) * rsz);
+  // in place (c == C, d == S) is allowed; every other overlap is not
+  if ((c != C && sc.overlaps(sC)) || (d != S && sd.overlaps(sS)) || sc.overlaps(sd) ||
+      sc.overlaps(sS) || sd.overlaps(sC) || sC.overlaps(sS))
+    return QFT_ERROR_OVERLAP;
+  DeviceGuard guard(plan->device);
+  if (!guard.ok) return hip_fail(hipErrorInvalidDevice);
+  return run_real(plan, 1, qftk::RealArgs{c, d, C, S}, (hipStream_t)stream);
 }
 
 }  // extern "C"

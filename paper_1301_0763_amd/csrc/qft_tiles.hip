@@ -62,7 +62,7 @@ __global__ __launch_bounds__(tile_threads(TL), 4) void tile_kernel_g(
     const int4 d = tiles[w];
     const int logn = __builtin_amdgcn_readfirstlane(d.x);
     const int count = __builtin_amdgcn_readfirstlane(d.z);
-    const GatherIO<DT, SWAP> io(x, X, offs + __builtin_amdgcn_readfirstlane(d.y));
+    const GatherIO<DT, SWAP> io(x, X, offs + __builtin_amdgcn_readfirstlane(d.y), logn);
     // The thread index is laundered once per tile: otherwise the compiler
     // hoists every thread-dependent LDS address of the bodies out of the
     // loop and keeps them all live (hundreds of registers, spills).
@@ -72,6 +72,65 @@ __global__ __launch_bounds__(tile_threads(TL), 4) void tile_kernel_g(
     __syncthreads();
   }
 }
+
+// Real-input kernels (KIND 0: rdft of real signals, KIND 1: DCT-0 and DST-0),
+// two real signals per transform slot, one workgroup per tile of T slots.
+template <int LOGN, int TL, int DT, int KIND>
+__global__ __launch_bounds__(tile_threads(TL)) void tile_kernel_r(RealArgs a, int64_t rows,
+                                                                   int64_t slots,
+                                                                   const float* sec) {
+  constexpr int T = 1 << (TL - LOGN);
+  constexpr int n = 1 << LOGN, h = n >> 1;
+  using R = typename RStore<DT>::T;
+  __shared__ float2 Wl[padded_cells<kPad>(1 << TL)];
+  const PadPtr<kPad> W{Wl, 0};
+  const int64_t t0 = (int64_t)blockIdx.x * T;
+  const int count = (int)min((int64_t)T, slots - t0);
+  const int64_t r0 = 2 * t0;  // first real signal of the tile
+  if constexpr (KIND == 0) {
+    using E = typename Store<DT>::T;
+    const RealPairIO<DT, LOGN> io{(const R*)a.in0 + r0 * n, (E*)a.out0 + r0 * (h + 1), rows - r0};
+    tile_body_s<LOGN, T, tile_threads(TL), kWave>(io, W, count, sec, (int)threadIdx.x, DevSync{},
+                                                  DevWaveSync{});
+  } else {
+    const R* c = (const R*)a.in0;
+    const R* d = (const R*)a.in1;
+    R* C = (R*)a.out0;
+    R* S = (R*)a.out1;
+    const DctDstIO<DT, LOGN> io{c ? c + r0 * (h + 1) : nullptr, d ? d + r0 * (h - 1) : nullptr,
+                                C ? C + r0 * (h + 1) : nullptr, S ? S + r0 * (h - 1) : nullptr,
+                                rows - r0};
+    tile_body_s<LOGN, T, tile_threads(TL), kWave>(io, W, count, sec, (int)threadIdx.x, DevSync{},
+                                                  DevWaveSync{});
+  }
+}
+
+template <int DT, int TL, int KIND, int LOGN>
+hipError_t launch_real_n(const TileGroup& g, const RealArgs& a, const float* sec,
+                         hipStream_t st) {
+  if constexpr (LOGN <= TL) {
+    if (g.ulog2n != LOGN) return launch_real_n<DT, TL, KIND, LOGN + 1>(g, a, sec, st);
+    if constexpr ((LOGN < kMinTileLog2 ? kMinTileLog2 : LOGN) == TL) {
+      hipLaunchKernelGGL((tile_kernel_r<LOGN, TL, DT, KIND>), dim3((unsigned)g.ntiles),
+                         dim3(tile_threads(TL)), 0, st, a, g.rows, g.ubatch, sec);
+      return hipGetLastError();
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int DT, int TL>
+hipError_t launch_real(const TileGroup& g, int kind, const RealArgs& a, const float* sec,
+                       hipStream_t st) {
+  if (g.tl != TL || g.ntiles <= 0 || g.d_tiles) return hipErrorInvalidValue;
+  return kind == 0 ? launch_real_n<DT, TL, 0, 1>(g, a, sec, st)
+                   : launch_real_n<DT, TL, 1, 1>(g, a, sec, st);
+}
+
+#if QFT_TILE_SWAP == 0
+template hipError_t launch_real<QFT_TILE_DT, QFT_TILE_TL>(const TileGroup&, int, const RealArgs&,
+                                                          const float*, hipStream_t);
+#endif
 
 template <int DT, int TL, bool SWAP, int LOGN>
 hipError_t launch_uniform(const TileGroup& g, const void* in, void* out, const float* sec,

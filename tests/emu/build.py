@@ -36,7 +36,9 @@ def load():
     L.emu_uneven.argtypes = [i, i, vp, vp, ctypes.POINTER(ctypes.c_int32), i64, i, i, i]
     L.emu_twopass.argtypes = [i, i, vp, vp, i, i64]
     L.emu_tile_s.argtypes = [i, i, vp, vp, i, i, vp]
-    for f in (L.emu_tile, L.emu_multipass, L.emu_uneven, L.emu_twopass, L.emu_tile_s):
+    L.emu_tile_real.argtypes = [i, i, i, i64, vp, vp, vp, vp]
+    for f in (L.emu_tile, L.emu_multipass, L.emu_uneven, L.emu_twopass, L.emu_tile_s,
+              L.emu_tile_real):
         f.restype = i
     return L
 

@@ -142,7 +142,7 @@ int tile_s_impl(const void* x, void* X, int Tact, const float* sec, const int64_
   TPtr W{lds.data(), 0, &tr, cells, kEmuPad};
   run_workgroup(NT, tr, [&](int tid, auto sync) {
     if (offs) {
-      const qftk::GatherIO<DT, SWAP> io((const E*)x, (E*)X, offs);
+      const qftk::GatherIO<DT, SWAP> io((const E*)x, (E*)X, offs, LOGN);
       qftk::tile_body_s<LOGN, T, NT, 64>(io, W, Tact, sec, tid, sync, sync);
     } else {
       const qftk::ContigIO<DT, SWAP, LOGN> io((const E*)x, (E*)X);
@@ -150,6 +150,48 @@ int tile_s_impl(const void* x, void* X, int Tact, const float* sec, const int64_
     }
   });
   return tr.oob ? -100 : (int)tr.races;
+}
+
+// One workgroup of the real-input tile kernel: KIND 0 = rdft of `rows` real
+// signals (two per transform slot), 1 = DCT-0/DST-0; rows <= 2 T.
+template <int DT, int LOGN, int KIND>
+int tile_real_impl(int64_t rows, const void* in0, const void* in1, void* out0, void* out1,
+                   const float* sec) {
+  using R = typename qftk::RStore<DT>::T;
+  using E = typename qftk::Store<DT>::T;
+  constexpr int TL = LOGN <= 12 ? 12 : LOGN;
+  constexpr int NT = TL == 12 ? 256 : (TL == 13 ? 512 : 1024);
+  constexpr int T = 1 << (TL - LOGN);
+  const int slots = (int)((rows + 1) / 2);
+  if (rows < 1 || slots > T) return -2;
+  const int64_t cells = (int64_t)T << LOGN;
+  std::vector<float2> lds(cells + (cells >> kEmuPad));
+  Tracker tr(NT);
+  TPtr W{lds.data(), 0, &tr, cells, kEmuPad};
+  run_workgroup(NT, tr, [&](int tid, auto sync) {
+    if constexpr (KIND == 0) {
+      const qftk::RealPairIO<DT, LOGN> io{(const R*)in0, (E*)out0, rows};
+      qftk::tile_body_s<LOGN, T, NT, 64>(io, W, slots, sec, tid, sync, sync);
+    } else {
+      const qftk::DctDstIO<DT, LOGN> io{(const R*)in0, (const R*)in1, (R*)out0, (R*)out1, rows};
+      qftk::tile_body_s<LOGN, T, NT, 64>(io, W, slots, sec, tid, sync, sync);
+    }
+  });
+  return tr.oob ? -100 : (int)tr.races;
+}
+
+template <int DT, int KIND>
+int tile_real_dispatch(int logn, int64_t rows, const void* in0, const void* in1, void* out0,
+                       void* out1, const float* sec) {
+  switch (logn) {
+#define QFT_EMU_REAL(L) \
+  case L: return tile_real_impl<DT, L, KIND>(rows, in0, in1, out0, out1, sec);
+    QFT_EMU_REAL(1) QFT_EMU_REAL(2) QFT_EMU_REAL(3) QFT_EMU_REAL(4) QFT_EMU_REAL(5)
+    QFT_EMU_REAL(6) QFT_EMU_REAL(7) QFT_EMU_REAL(8) QFT_EMU_REAL(9) QFT_EMU_REAL(10)
+    QFT_EMU_REAL(11) QFT_EMU_REAL(12) QFT_EMU_REAL(13) QFT_EMU_REAL(14)
+#undef QFT_EMU_REAL
+    default: return -1;
+  }
 }
 
 template <int DT, bool SWAP>
@@ -402,6 +444,17 @@ int emu_tile_s(int dt, int swap, const void* x, void* X, int logn, int Tact,
                            : tile_s_dispatch<0, false>(x, X, logn, Tact, sec.data(), offs);
   return swap ? tile_s_dispatch<1, true>(x, X, logn, Tact, sec.data(), offs)
               : tile_s_dispatch<1, false>(x, X, logn, Tact, sec.data(), offs);
+}
+
+// One workgroup of the real-input tile kernel (kind 0: rdft in0 -> out0;
+// kind 1: DCT-0 in0 -> out0 and DST-0 in1 -> out1, either pair may be null).
+int emu_tile_real(int kind, int dt, int logn, int64_t rows, const void* in0, const void* in1,
+                  void* out0, void* out1) {
+  std::vector<float> sec = secants(logn < 3 ? 3 : logn);
+  if (dt == 0) return kind == 0 ? tile_real_dispatch<0, 0>(logn, rows, in0, in1, out0, out1, sec.data())
+                                : tile_real_dispatch<0, 1>(logn, rows, in0, in1, out0, out1, sec.data());
+  return kind == 0 ? tile_real_dispatch<1, 0>(logn, rows, in0, in1, out0, out1, sec.data())
+                   : tile_real_dispatch<1, 1>(logn, rows, in0, in1, out0, out1, sec.data());
 }
 
 int emu_multipass(int dt, int swap, const void* x, void* X, int logn, int64_t batch,

@@ -153,3 +153,18 @@ def test_schedule_entry_points_reject_null_plan():
     ms = (ctypes.c_double * 4)()
     assert L.qft_plan_autotune(None, 8, 8, None, 5, ms, 4, ctypes.byref(c)) == \
         _lib.QFT_ERROR_INVALID_VALUE
+
+
+def test_real_entry_points_reject_bad_arguments():
+    L = _lib.lib()
+    h = ctypes.c_void_p(1)
+    assert L.qft_plan_create_real(None, 10, 4, 0, 0) == _lib.QFT_ERROR_INVALID_VALUE
+    assert L.qft_plan_create_real(ctypes.byref(h), 0, 4, 0, 0) == _lib.QFT_ERROR_INVALID_SIZE
+    assert h.value is None
+    assert L.qft_plan_create_real(ctypes.byref(h), 25, 4, 0, 0) == _lib.QFT_ERROR_INVALID_SIZE
+    assert L.qft_plan_create_real(ctypes.byref(h), 10, 0, 0, 0) == _lib.QFT_ERROR_INVALID_VALUE
+    assert L.qft_plan_create_real(ctypes.byref(h), 10, 4, 5, 0) == _lib.QFT_ERROR_INVALID_VALUE
+    # longer than one workgroup's tile: not built for real input
+    assert L.qft_plan_create_real(ctypes.byref(h), 15, 4, 0, 0) == _lib.QFT_ERROR_UNSUPPORTED
+    assert L.qft_exec_rdft(None, 8, 8, None) == _lib.QFT_ERROR_INVALID_VALUE
+    assert L.qft_exec_dct0_dst0(None, 8, None, 8, None, None) == _lib.QFT_ERROR_INVALID_VALUE

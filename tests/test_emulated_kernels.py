@@ -245,3 +245,64 @@ def test_specialised_tile_offset_list(emu, logn, swap):
     # slots that hold no transform of the tile are left untouched
     free = np.setdiff1d(np.arange(Tact + 2), slots)
     assert np.all(np.isnan(out[free[0] * N:(free[0] + 1) * N]))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+@pytest.mark.parametrize("logn", [1, 2, 3, 5, 8, 10, 12, 13])
+@pytest.mark.parametrize("odd", [0, 1])
+def test_specialised_tile_real_input(emu, logn, odd):
+    """Real-input tile: two real signals per transform slot (lanes x, y), the
+    half spectrum X(k) = C(k) - i S(k), k = 0..N/2 of each (rdft, Sec. 4.2),
+    against the oracle's rdft; an odd number of signals leaves the last
+    slot's second lane empty."""
+    N = 1 << logn
+    T = max(1, 4096 // N) if logn <= 12 else 1
+    rows = min(2 * T, 6) - odd
+    x = np.ascontiguousarray(workloads.normal(1200 + logn, (rows, N)).real.astype(np.float32))
+    out = np.full((rows, N // 2 + 1), np.nan + 1j * np.nan, dtype=np.complex64)
+    races = emu.emu_tile_real(0, 0, logn, rows, _ptr(x), None, _ptr(out), None)
+    assert races == 0, races
+    re, im = Q.rdft(x.astype(np.float64), N, Q.Ops())
+    ref = re.astype(np.complex128)
+    if N > 2:
+        ref[..., 1:N // 2] += 1j * im
+    assert D.relative_l2(out.astype(np.complex128), ref).max() <= _tol(logn)
+    # and the definition of the half spectrum
+    np.testing.assert_allclose(out, np.fft.fft(x.astype(np.float64))[..., :N // 2 + 1],
+                               rtol=0, atol=_tol(logn) * np.sqrt(N) * 4)
+
+
+@pytest.mark.parametrize("logn", [1, 2, 3, 4, 6, 9, 12])
+@pytest.mark.parametrize("which", ["both", "dct", "dst"])
+def test_specialised_tile_dct0_dst0(emu, logn, which):
+    """DCT-0 and DST-0 entry point: the heap fed straight with c(n) and d(n),
+    C(k) and S(k) read out unfolded, against the oracle's dct and dst."""
+    N = 1 << logn
+    h = N // 2
+    if which == "dst" and h - 1 == 0:
+        pytest.skip("the DST-0 of N = 2 is empty")
+    T = max(1, 4096 // N) if logn <= 12 else 1
+    rows = min(5, 2 * T)
+    c = np.ascontiguousarray(workloads.uniform(1300 + logn, (rows, h + 1)).real.astype(np.float32))
+    d = np.ascontiguousarray(workloads.uniform(1400 + logn, (rows, max(h - 1, 1))).real
+                             .astype(np.float32)[:, :h - 1])
+    C = np.full((rows, h + 1), np.nan, np.float32)
+    S = np.full((rows, max(h - 1, 0)), np.nan, np.float32)
+    use_c, use_d = which in ("both", "dct"), which in ("both", "dst") and h > 1
+    races = emu.emu_tile_real(1, 0, logn, rows, _ptr(c) if use_c else None,
+                              _ptr(d) if use_d else None, _ptr(C) if use_c else None,
+                              _ptr(S) if use_d else None)
+    assert races == 0, races
+    if use_c:
+        refC = Q.dct(c.astype(np.float64), N, Q.Ops())
+        assert D.relative_l2(C.astype(np.float64), refC).max() <= _tol(logn)
+    else:
+        assert np.all(np.isnan(C))
+    if use_d:
+        refS = Q.dst(d.astype(np.float64), N, Q.Ops())
+        assert D.relative_l2(S.astype(np.float64), refS).max() <= _tol(logn)
+    elif h > 1:
+        assert np.all(np.isnan(S))

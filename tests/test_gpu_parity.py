@@ -340,3 +340,98 @@ def test_uneven_schedules_and_autotune():
     with pytest.raises(qft.QFTError):
         plan.schedule = len(names)
     plan.close()
+
+
+def _rdft_ref(x):
+    x = np.asarray(x, dtype=np.float64)
+    N = x.shape[-1]
+    re, im = Q.rdft(x, N, Q.Ops())
+    ref = re.astype(np.complex128)
+    if N > 2:
+        ref[..., 1:N // 2] += 1j * im
+    return ref
+
+
+@pytest.mark.parametrize("logn", range(1, 15))
+def test_rdft_all_tile_sizes(logn):
+    """Real-input transform (rdft, Sec. 4.2): half spectrum against the
+    oracle's rdft, with an odd number of signals (the last slot's second lane
+    empty)."""
+    N = 1 << logn
+    B = 7 if logn > 10 else 33
+    say(f"rdft: N=2^{logn} B={B}")
+    x = np.ascontiguousarray(workloads.normal(5000 + logn, (B, N)).real.astype(np.float32))
+    H = qft.rdft(torch.from_numpy(x).to(DEV))
+    torch.cuda.synchronize()
+    assert H.shape == (B, N // 2 + 1) and H.dtype == torch.complex64
+    err = D.relative_l2(H.cpu().numpy().astype(np.complex128), _rdft_ref(x)).max()
+    assert err <= tol(logn), err
+
+
+def test_rdft_matches_complex_path_and_fp16():
+    """The rdft of x equals the first N/2+1 bins of the complex transform of
+    x + 0i; FP16 storage within the output-rounding bound."""
+    say("rdft vs complex, fp16")
+    logn, B = 12, 64
+    x = np.ascontiguousarray(workloads.uniform(6000, (B, 1 << logn)).real.astype(np.float32))
+    xt = torch.from_numpy(x).to(DEV)
+    H = qft.rdft(xt)
+    X = qft.fft(xt.to(torch.complex64))
+    torch.cuda.synchronize()
+    h = H.cpu().numpy().astype(np.complex128)
+    full = X.cpu().numpy().astype(np.complex128)[:, :(1 << logn) // 2 + 1]
+    assert D.relative_l2(h, full).max() <= tol(logn)
+    H16 = qft.rdft(xt.half())
+    torch.cuda.synchronize()
+    h16 = H16.view(torch.float16).reshape(B, -1, 2).float().cpu().numpy()
+    ref16 = _rdft_ref(x.astype(np.float16).astype(np.float64))
+    assert D.relative_l2(h16[..., 0] + 1j * h16[..., 1], ref16).max() < 1e-3
+
+
+@pytest.mark.parametrize("logn", [1, 2, 3, 6, 10, 13, 14])
+def test_dct0_dst0(logn):
+    """Standalone DCT-0 / DST-0 (dct on s_dc_tt, dst on s_ds_tt) against the
+    oracle, together, alone, and in place."""
+    N = 1 << logn
+    h = N // 2
+    B = 5
+    say(f"dct0/dst0: N=2^{logn} B={B}")
+    c = np.ascontiguousarray(workloads.uniform(7000 + logn, (B, h + 1)).real.astype(np.float32))
+    d = np.ascontiguousarray(workloads.uniform(7100 + logn, (B, max(h - 1, 1))).real
+                             .astype(np.float32)[:, :h - 1])
+    refC = Q.dct(c.astype(np.float64), N, Q.Ops())
+    ct, dt_ = torch.from_numpy(c).to(DEV), torch.from_numpy(d.copy()).to(DEV)
+    plan = qft.RealPlan(logn, B)
+    C, S = plan.dct0_dst0(ct, dt_ if h > 1 else None)
+    C1 = qft.dct0(ct)
+    torch.cuda.synchronize()
+    assert D.relative_l2(C.cpu().numpy().astype(np.float64), refC).max() <= tol(logn)
+    assert torch.equal(C, C1)
+    if h > 1:
+        refS = Q.dst(d.astype(np.float64), N, Q.Ops())
+        assert D.relative_l2(S.cpu().numpy().astype(np.float64), refS).max() <= tol(logn)
+        assert torch.equal(qft.dst0(dt_), S)
+        # in place: c -> C and d -> S in the input buffers
+        qft.qft_exec_dct0_dst0(plan.handle, ct.data_ptr(), dt_.data_ptr(), ct.data_ptr(),
+                               dt_.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        assert torch.equal(ct, C) and torch.equal(dt_, S)
+    plan.close()
+
+
+def test_real_plan_errors():
+    say("real plan error codes")
+    plan = qft.RealPlan(10, 4)
+    x = torch.zeros(4, 1024, device=DEV)
+    y = torch.zeros(4, 1024, dtype=torch.complex64, device=DEV)
+    with pytest.raises(qft.QFTError):  # complex exec on a real plan
+        qft.qft_exec_fwd(plan.handle, y.data_ptr(), y.data_ptr(), 0)
+    with pytest.raises(qft.QFTError):  # overlapping rdft buffers
+        qft.qft_exec_rdft(plan.handle, x.data_ptr(), x.data_ptr() + 64, 0)
+    with pytest.raises(qft.QFTError):  # a half-given pair
+        qft.qft_exec_dct0_dst0(plan.handle, x.data_ptr(), None, None, None, 0)
+    cplan = qft.Plan(10, 4)
+    with pytest.raises(qft.QFTError):  # rdft on a complex plan
+        qft.qft_exec_rdft(cplan.handle, x.data_ptr(), y.data_ptr(), 0)
+    plan.close()
+    cplan.close()
