@@ -151,7 +151,9 @@ qft_status qft_plan_autotune(qft_plan_t plan, const void* in, void* out, void* s
 /*
  * Real-input plans (the rdft, dct and dst functions of Sec. 4.2 and Sec.
  * 5.2 as entry points of their own).  `batch` real signals of N = 2^log2n
- * points, 1 <= log2n <= 14 (longer ones: QFT_ERROR_UNSUPPORTED).  Storage:
+ * points, 1 <= log2n <= QFT_MAX_LOG2N (up to 2^14 in one workgroup's tile,
+ * longer ones through the multi-pass path with a device scratch of
+ * 2 * ceil(batch/2) * N complex FP32 values).  Storage:
  * QFT_C32 = FP32 reals (and complex FP32 outputs), QFT_C16 = FP16 (complex
  * FP16 outputs), FP32 arithmetic either way.  Two real signals travel
  * through the transform together, one in each lane of a complex cell, so a

@@ -914,6 +914,44 @@ QFT_HD void mp_combine_item(WP W, typename Store<DT>::T* X, int logn, int64_t i)
   }
 }
 
+// Fold and combine items through a tile IO accessor (real-input plans):
+// item i < slots * N/2, transform slot t = i / (N/2).
+template <class IO, typename WP>
+QFT_HD void mp_fold_io_item(const IO& io, WP W, int logn, int64_t i) {
+  const int n = 1 << logn, h = n >> 1;
+  const int64_t t = i >> (logn - 1);
+  const int m = (int)(i & (h - 1));
+  auto w = W + (t << logn);
+  typename IO::Raw r;
+  io.fetch((int)t, m, r);
+  float2 lo, hi;
+  io.fold(r, m, lo, hi);
+  if (m == 0) {
+    w[0] = lo;
+    w[h] = hi;
+  } else {
+    const int l = __builtin_ctz(m);
+    const int cell = (n >> (l + 2)) + (m >> (l + 1));
+    w[cell] = lo;
+    w[h + cell] = hi;
+  }
+}
+
+template <class IO, typename WP>
+QFT_HD void mp_combine_io_item(const IO& io, WP W, int logn, int64_t i) {
+  const int n = 1 << logn, h = n >> 1;
+  const int64_t t = i >> (logn - 1);
+  const int k = (int)(i & (h - 1));
+  auto w = W + (t << logn);
+  const auto o = io.out((int)t);
+  if (k == 0) {
+    io.put_edge(o, 0, w[0]);
+    io.put_edge(o, h, w[h]);
+  } else {
+    io.put(o, n, k, w[k], w[h + k]);
+  }
+}
+
 // forward group item i < 2*batch * 2^(logn-K-2): K rounds ending at
 // S = 2^(hi-K+1) >= 4, in place (groups are closed cell sets).
 template <int K, typename WP>
@@ -1622,7 +1660,6 @@ template <int DT, int LOGN>
 struct RealPairIO {
   using R = typename RStore<DT>::T;
   using E = typename Store<DT>::T;
-  static constexpr int n = 1 << LOGN, h = n >> 1;
   struct Raw {
     float2 a, b;
   };
@@ -1633,14 +1670,17 @@ struct RealPairIO {
   const R* x;
   E* X;
   int64_t rows;
+  int lg = LOGN;  // log2 N: the template's, or given at run time when LOGN = 0
+  QFT_HD int nn() const { return LOGN ? (1 << LOGN) : (1 << lg); }
   QFT_HD bool has_b(int t) const { return 2 * (int64_t)t + 1 < rows; }
   QFT_HD float2 pair(int t, int i) const {
     const int64_t r0 = 2 * (int64_t)t;
-    const float va = RStore<DT>::ld(x, r0 * n + i);
-    const float vb = has_b(t) ? RStore<DT>::ld(x, (r0 + 1) * n + i) : 0.f;
+    const float va = RStore<DT>::ld(x, r0 * nn() + i);
+    const float vb = has_b(t) ? RStore<DT>::ld(x, (r0 + 1) * nn() + i) : 0.f;
     return make_float2(va, vb);
   }
   QFT_HD void fetch(int t, int m, Raw& r) const {
+    const int n = nn(), h = n >> 1;
     r.a = pair(t, m);
     r.b = pair(t, m == 0 ? h : n - m);
   }
@@ -1648,7 +1688,7 @@ struct RealPairIO {
     ComplexIO<DT, false>::fold(typename ComplexIO<DT, false>::Raw{r.a, r.b}, m, lo, hi);
   }
   QFT_HD Out out(int t) const {
-    const int64_t r0 = 2 * (int64_t)t;
+    const int64_t r0 = 2 * (int64_t)t, h = nn() >> 1;
     return Out{X + r0 * (h + 1), has_b(t) ? X + (r0 + 1) * (h + 1) : nullptr};
   }
   QFT_HD static void put(const Out& o, int, int k, float2 C, float2 S) {
@@ -1671,7 +1711,6 @@ struct RealPairIO {
 template <int DT, int LOGN>
 struct DctDstIO {
   using R = typename RStore<DT>::T;
-  static constexpr int n = 1 << LOGN, h = n >> 1;
   struct Raw {
     float2 a, b;
   };
@@ -1686,6 +1725,8 @@ struct DctDstIO {
   R* C;
   R* S;
   int64_t rows;
+  int lg = LOGN;  // log2 N: the template's, or given at run time when LOGN = 0
+  QFT_HD int nn() const { return LOGN ? (1 << LOGN) : (1 << lg); }
   QFT_HD bool has_b(int t) const { return 2 * (int64_t)t + 1 < rows; }
   QFT_HD float2 pair(const R* p, int len, int t, int i) const {
     if (!p) return make_float2(0.f, 0.f);
@@ -1695,6 +1736,7 @@ struct DctDstIO {
     return make_float2(va, vb);
   }
   QFT_HD void fetch(int t, int m, Raw& r) const {
+    const int h = nn() >> 1;
     if (m == 0) {
       r.a = pair(c, h + 1, t, 0);
       r.b = pair(c, h + 1, t, h);
@@ -1708,7 +1750,7 @@ struct DctDstIO {
     hi = r.b;
   }
   QFT_HD Out out(int t) const {
-    const int64_t r0 = 2 * (int64_t)t;
+    const int64_t r0 = 2 * (int64_t)t, h = nn() >> 1;
     const bool b = has_b(t);
     return Out{C ? C + r0 * (h + 1) : nullptr, (C && b) ? C + (r0 + 1) * (h + 1) : nullptr,
                S ? S + r0 * (h - 1) : nullptr, (S && b) ? S + (r0 + 1) * (h - 1) : nullptr};

@@ -69,6 +69,20 @@ __global__ __launch_bounds__(MP_BLOCK) void mp_chain_kernel(float2* W, int logn,
   QFT_GRID_STRIDE(i, batch * chain_groups(p)) mp_chain_item(W, logn, p, i);
 }
 
+// Multi-pass fold and combine of real-input plans (IO = RealPairIO or
+// DctDstIO with the length given at run time).
+template <class IO>
+__global__ __launch_bounds__(MP_BLOCK) void mp_fold_io_kernel(IO io, float2* W, int logn,
+                                                              int64_t slots) {
+  QFT_GRID_STRIDE(i, slots << (logn - 1)) mp_fold_io_item(io, W, logn, i);
+}
+
+template <class IO>
+__global__ __launch_bounds__(MP_BLOCK) void mp_combine_io_kernel(IO io, const float2* W,
+                                                                 int logn, int64_t slots) {
+  QFT_GRID_STRIDE(i, slots << (logn - 1)) mp_combine_io_item(io, W, logn, i);
+}
+
 #undef QFT_GRID_STRIDE
 
 template <int MC_LOG2, int BLOCK>
@@ -348,6 +362,50 @@ qft_status launch_multipass(const void* in, void* out, int log2n, int64_t batch,
   return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
 }
 
+// Multi-pass executor of a real-input plan: the real fold / combine through
+// the plan's IO accessor, the middle kernels of the complex path on the
+// transform slots (two real signals each).
+template <class IO>
+struct GpuMultipassReal {
+  GpuMultipass<0, false> mid;
+  IO io;
+  void fold() {
+    hipLaunchKernelGGL((qftk::mp_fold_io_kernel<IO>), dim3(mid.g_elem()), dim3(qftk::MP_BLOCK),
+                       0, mid.st, io, mid.cur, mid.logn, mid.batch);
+  }
+  void fwd(int K, int hi) { mid.fwd(K, hi); }
+  void segment() { mid.segment(); }
+  void bwd(int s) { mid.bwd(s); }
+  void chain(int p) { mid.chain(p); }
+  void combine() {
+    hipLaunchKernelGGL((qftk::mp_combine_io_kernel<IO>), dim3(mid.g_elem()),
+                       dim3(qftk::MP_BLOCK), 0, mid.st, io, (const float2*)mid.cur, mid.logn,
+                       mid.batch);
+  }
+};
+
+template <int DT>
+qft_status launch_multipass_real(int kind, const qftk::RealArgs& a, int log2n, int64_t rows,
+                                 const float* sec, float2* W0, float2* W1, hipStream_t st) {
+  using R = typename qftk::RStore<DT>::T;
+  using E = typename qftk::Store<DT>::T;
+  const int64_t slots = (rows + 1) / 2;
+  if (slots * qftk::mp_segment_blocks(log2n, kSegLog2) > 0x7fffffff) return QFT_ERROR_INVALID_VALUE;
+  const GpuMultipass<0, false> mid{nullptr, nullptr, log2n, slots, sec, W0, W1, st};
+  if (kind == 0) {
+    const qftk::RealPairIO<DT, 0> io{(const R*)a.in0, (E*)a.out0, rows, log2n};
+    GpuMultipassReal<qftk::RealPairIO<DT, 0>> ex{mid, io};
+    qftk::multipass_schedule(ex, log2n, kSegLog2);
+  } else {
+    const qftk::DctDstIO<DT, 0> io{(const R*)a.in0, (const R*)a.in1, (R*)a.out0, (R*)a.out1,
+                                   rows, log2n};
+    GpuMultipassReal<qftk::DctDstIO<DT, 0>> ex{mid, io};
+    qftk::multipass_schedule(ex, log2n, kSegLog2);
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
+}
+
 // Two-pass path (N = 2^15, 2^16): pass A into the heap buffer W, pass B to X.
 template <int DT, bool SWAP>
 qft_status launch_twopass(const void* in, void* out, int log2n, int64_t batch, const float* sec,
@@ -443,6 +501,13 @@ struct Span {
 };
 
 qft_status run_real(const qft_plan_s* p, int kind, const qftk::RealArgs& a, hipStream_t st) {
+  if (p->log2n > qftk::kMaxTileLog2) {
+    float2* W0 = p->d_work;
+    float2* W1 = p->d_work + p->work_cells;
+    return p->dtype == QFT_C16
+               ? launch_multipass_real<1>(kind, a, p->log2n, p->batch, p->d_sec, W0, W1, st)
+               : launch_multipass_real<0>(kind, a, p->log2n, p->batch, p->d_sec, W0, W1, st);
+  }
   const qftk::TileGroup& g = p->schedules[p->chosen].groups[0];
   hipError_t e = hipErrorInvalidValue;
   const bool h16 = p->dtype == QFT_C16;
@@ -733,7 +798,6 @@ qft_status qft_plan_create_real(qft_plan_t* plan, int log2n, int64_t batch, qft_
   *plan = nullptr;
   if (batch <= 0 || (dtype != QFT_C32 && dtype != QFT_C16)) return QFT_ERROR_INVALID_VALUE;
   if (log2n < 1 || log2n > QFT_MAX_LOG2N) return QFT_ERROR_INVALID_SIZE;
-  if (log2n > qftk::kMaxTileLog2) return QFT_ERROR_UNSUPPORTED;
   if (batch > ((int64_t)1 << 40) >> log2n) return QFT_ERROR_INVALID_VALUE;
   int cus = 0;
   qft_status s = check_device(device, &cus);
@@ -753,18 +817,25 @@ qft_status qft_plan_create_real(qft_plan_t* plan, int log2n, int64_t batch, qft_
   // Table 2, RDFT row: (N log N - 3N)/2 + 2 multiplications, (3 N log N - 5N)/2 + 4 additions
   p->flops_actual = (2.0 * (double)N * log2n - 4.0 * (double)N + 6.0) * (double)batch;
   p->real_algo_bytes = batch * (N * rsz + (N / 2 + 1) * 2 * rsz);
-  const int tl = std::max(qftk::kMinTileLog2, log2n);
-  const int64_t slots = (batch + 1) / 2, per = (int64_t)1 << (tl - log2n);
-  const int64_t ntiles = (slots + per - 1) / per;
-  if (ntiles > 0x7fffffff) {
-    free_plan(p);
-    return QFT_ERROR_INVALID_VALUE;
+  const int64_t slots = (batch + 1) / 2;
+  if (log2n > qftk::kMaxTileLog2) {
+    // multi-pass path on the transform slots, heap buffers of slots * N cells
+    p->work_cells = slots << log2n;
+    p->schedules.push_back(Schedule{"multi-pass/real", {}});
+  } else {
+    const int tl = std::max(qftk::kMinTileLog2, log2n);
+    const int64_t per = (int64_t)1 << (tl - log2n);
+    const int64_t ntiles = (slots + per - 1) / per;
+    if (ntiles > 0x7fffffff) {
+      free_plan(p);
+      return QFT_ERROR_INVALID_VALUE;
+    }
+    Schedule sc;
+    sc.name = "t" + std::to_string(tl) + ":" + std::to_string(log2n) + "/real";
+    sc.groups.push_back(qftk::TileGroup{tl, (int)ntiles, (int)ntiles, nullptr, nullptr, log2n,
+                                        slots, batch});
+    p->schedules.push_back(sc);
   }
-  Schedule sc;
-  sc.name = "t" + std::to_string(tl) + ":" + std::to_string(log2n) + "/real";
-  sc.groups.push_back(qftk::TileGroup{tl, (int)ntiles, (int)ntiles, nullptr, nullptr, log2n, slots,
-                                      batch});
-  p->schedules.push_back(sc);
   s = alloc_common(p);
   if (s != QFT_SUCCESS) {
     free_plan(p);

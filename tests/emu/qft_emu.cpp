@@ -254,6 +254,8 @@ struct EmuMultipass {
   int64_t cells;
   Tracker gtr{1};
   int64_t races = 0;
+  // real-input plans: fold and combine through an IO accessor instead
+  std::function<void(TPtr, int64_t)> fold_io, combine_io;
   template <class F>
   void items(int64_t total, F f) {
     tl_slot = 0;
@@ -265,6 +267,10 @@ struct EmuMultipass {
   }
   TPtr G(float2* p) { return TPtr{p, 0, &gtr, cells}; }
   void fold() {
+    if (fold_io) {
+      items(batch << (logn - 1), [&](int64_t i) { fold_io(G(cur), i); });
+      return;
+    }
     items(batch << (logn - 1), [&](int64_t i) { qftk::mp_fold_item<DT, SWAP>(x, G(cur), logn, i); });
   }
   void fwd(int K, int hi) {
@@ -313,6 +319,10 @@ struct EmuMultipass {
     items(batch * qftk::chain_groups(p), [&](int64_t i) { qftk::mp_chain_item(G(cur), logn, p, i); });
   }
   void combine() {
+    if (combine_io) {
+      items(batch << (logn - 1), [&](int64_t i) { combine_io(G(cur), i); });
+      return;
+    }
     items(batch << (logn - 1), [&](int64_t i) { qftk::mp_combine_item<DT, SWAP>(G(cur), X, logn, i); });
   }
 };
@@ -325,6 +335,31 @@ int multipass_impl(const void* x, void* X, int logn, int64_t batch, int seg_log2
   std::vector<float2> w0((size_t)batch << logn), w1((size_t)batch << logn);
   EmuMultipass<DT, SWAP> ex{(const E*)x, (E*)X, logn, batch, seg_log2, nthr, sec,
                             w0.data(), w1.data(), (int64_t)batch << logn};
+  qftk::multipass_schedule(ex, logn, seg_log2);
+  if (ex.races < 0 || ex.gtr.oob) return -4;
+  return (int)(ex.races + ex.gtr.races);
+}
+
+// Multi-pass path of a real-input plan (kind 0: rdft, 1: DCT-0/DST-0).
+template <int DT>
+int multipass_real_impl(int kind, int logn, int64_t rows, const void* in0, const void* in1,
+                        void* out0, void* out1, int seg_log2, int nthr, const float* sec) {
+  using R = typename qftk::RStore<DT>::T;
+  using E = typename qftk::Store<DT>::T;
+  if (logn < seg_log2 + 3) return -3;
+  const int64_t slots = (rows + 1) / 2;
+  std::vector<float2> w0((size_t)slots << logn), w1((size_t)slots << logn);
+  EmuMultipass<DT, false> ex{nullptr, nullptr, logn, slots, seg_log2, nthr, sec,
+                             w0.data(), w1.data(), (int64_t)slots << logn};
+  const qftk::RealPairIO<DT, 0> rio{(const R*)in0, (E*)out0, rows, logn};
+  const qftk::DctDstIO<DT, 0> dio{(const R*)in0, (const R*)in1, (R*)out0, (R*)out1, rows, logn};
+  if (kind == 0) {
+    ex.fold_io = [&](TPtr W, int64_t i) { qftk::mp_fold_io_item(rio, W, logn, i); };
+    ex.combine_io = [&](TPtr W, int64_t i) { qftk::mp_combine_io_item(rio, W, logn, i); };
+  } else {
+    ex.fold_io = [&](TPtr W, int64_t i) { qftk::mp_fold_io_item(dio, W, logn, i); };
+    ex.combine_io = [&](TPtr W, int64_t i) { qftk::mp_combine_io_item(dio, W, logn, i); };
+  }
   qftk::multipass_schedule(ex, logn, seg_log2);
   if (ex.races < 0 || ex.gtr.oob) return -4;
   return (int)(ex.races + ex.gtr.races);
@@ -455,6 +490,17 @@ int emu_tile_real(int kind, int dt, int logn, int64_t rows, const void* in0, con
                                 : tile_real_dispatch<0, 1>(logn, rows, in0, in1, out0, out1, sec.data());
   return kind == 0 ? tile_real_dispatch<1, 0>(logn, rows, in0, in1, out0, out1, sec.data())
                    : tile_real_dispatch<1, 1>(logn, rows, in0, in1, out0, out1, sec.data());
+}
+
+// Multi-pass path of a real-input plan with 2^seg_log2-cell segments.
+int emu_multipass_real(int kind, int dt, int logn, int64_t rows, const void* in0,
+                       const void* in1, void* out0, void* out1, int seg_log2, int nthr) {
+  if (logn < 4 || logn > 24 || rows < 1 || nthr < 1) return -1;
+  std::vector<float> sec = secants(logn);
+  return dt == 0 ? multipass_real_impl<0>(kind, logn, rows, in0, in1, out0, out1, seg_log2, nthr,
+                                          sec.data())
+                 : multipass_real_impl<1>(kind, logn, rows, in0, in1, out0, out1, seg_log2, nthr,
+                                          sec.data());
 }
 
 int emu_multipass(int dt, int swap, const void* x, void* X, int logn, int64_t batch,

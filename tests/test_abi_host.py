@@ -164,7 +164,5 @@ def test_real_entry_points_reject_bad_arguments():
     assert L.qft_plan_create_real(ctypes.byref(h), 25, 4, 0, 0) == _lib.QFT_ERROR_INVALID_SIZE
     assert L.qft_plan_create_real(ctypes.byref(h), 10, 0, 0, 0) == _lib.QFT_ERROR_INVALID_VALUE
     assert L.qft_plan_create_real(ctypes.byref(h), 10, 4, 5, 0) == _lib.QFT_ERROR_INVALID_VALUE
-    # longer than one workgroup's tile: not built for real input
-    assert L.qft_plan_create_real(ctypes.byref(h), 15, 4, 0, 0) == _lib.QFT_ERROR_UNSUPPORTED
     assert L.qft_exec_rdft(None, 8, 8, None) == _lib.QFT_ERROR_INVALID_VALUE
     assert L.qft_exec_dct0_dst0(None, 8, None, 8, None, None) == _lib.QFT_ERROR_INVALID_VALUE

@@ -306,3 +306,34 @@ def test_specialised_tile_dct0_dst0(emu, logn, which):
         assert D.relative_l2(S.astype(np.float64), refS).max() <= _tol(logn)
     elif h > 1:
         assert np.all(np.isnan(S))
+
+
+@pytest.mark.parametrize("seg,logn", [(3, 6), (4, 9), (5, 11)])
+@pytest.mark.parametrize("rows", [3, 4])
+def test_multipass_real_input(emu, seg, logn, rows):
+    """Real-input plans longer than a tile: the multi-pass schedule (small
+    segments so that every global stage occurs) with the real fold and the
+    half-spectrum / DCT-0 / DST-0 read-out."""
+    N, h = 1 << logn, 1 << (logn - 1)
+    x = np.ascontiguousarray(workloads.normal(1500 + logn, (rows, N)).real.astype(np.float32))
+    out = np.zeros((rows, h + 1), np.complex64)
+    assert emu.emu_multipass_real(0, 0, logn, rows, _ptr(x), None, _ptr(out), None, seg, 16) == 0
+    assert D.relative_l2(out.astype(np.complex128), _rdft_emu_ref(x)).max() <= _tol(logn)
+    c = np.ascontiguousarray(workloads.uniform(1600 + logn, (rows, h + 1)).real.astype(np.float32))
+    d = np.ascontiguousarray(workloads.uniform(1700 + logn, (rows, h - 1)).real.astype(np.float32))
+    C = np.zeros_like(c)
+    S = np.zeros_like(d)
+    assert emu.emu_multipass_real(1, 0, logn, rows, _ptr(c), _ptr(d), _ptr(C), _ptr(S), seg,
+                                  16) == 0
+    assert D.relative_l2(C.astype(np.float64), Q.dct(c.astype(np.float64), N, Q.Ops())).max() \
+        <= _tol(logn)
+    assert D.relative_l2(S.astype(np.float64), Q.dst(d.astype(np.float64), N, Q.Ops())).max() \
+        <= _tol(logn)
+
+
+def _rdft_emu_ref(x):
+    N = x.shape[-1]
+    re, im = Q.rdft(x.astype(np.float64), N, Q.Ops())
+    ref = re.astype(np.complex128)
+    ref[..., 1:N // 2] += 1j * im
+    return ref

@@ -435,3 +435,22 @@ def test_real_plan_errors():
         qft.qft_exec_rdft(cplan.handle, x.data_ptr(), y.data_ptr(), 0)
     plan.close()
     cplan.close()
+
+
+@pytest.mark.parametrize("logn,B", [(15, 3), (16, 4), (18, 1)])
+def test_real_input_multipass_sizes(logn, B):
+    """Real-input plans beyond a tile: the multi-pass path on transform slots
+    of two real signals, rdft and DCT-0/DST-0 against the oracle."""
+    N, h = 1 << logn, 1 << (logn - 1)
+    say(f"real multi-pass: N=2^{logn} B={B}")
+    x = np.ascontiguousarray(workloads.normal(8000 + logn, (B, N)).real.astype(np.float32))
+    H = qft.rdft(torch.from_numpy(x).to(DEV))
+    torch.cuda.synchronize()
+    ref = OB.cdft(x.astype(np.complex128))[:, :h + 1]
+    assert D.relative_l2(H.cpu().numpy().astype(np.complex128), ref).max() <= tol(logn)
+    c = np.ascontiguousarray(workloads.uniform(8100 + logn, (B, h + 1)).real.astype(np.float32))
+    C = qft.dct0(torch.from_numpy(c).to(DEV))
+    torch.cuda.synchronize()
+    refC = Q.dct(c.astype(np.float64), N, Q.Ops()) if logn <= 16 else None
+    if refC is not None:
+        assert D.relative_l2(C.cpu().numpy().astype(np.float64), refC).max() <= tol(logn)
