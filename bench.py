@@ -142,6 +142,20 @@ def extra_workloads(dev, stream):
     }
     up.close()
     up16.close()
+    # c3: one transform of N = 2^24 (multi-pass path)
+    x3, _, _ = workloads.make("c3")
+    x3t = torch.from_numpy(x3).to(dev)
+    y3 = torch.empty_like(x3t)
+    p3 = qft.Plan(24, 1)
+    ms3 = time_ms(lambda: qft.qft_exec_fwd(p3.handle, x3t.data_ptr(), y3.data_ptr(), sp),
+                  stream, 10, 2)
+    out["c3_single_large"] = {
+        "workload": "c3: N=2^24 x 1, 8 tones + N(0, 1e-3) noise, seed 2 (multi-pass path)",
+        "ms": round(ms3, 5), "GBps": round(p3.info["algo_bytes"] / (ms3 * 1e-3) / 1e9, 1),
+        "GFLOPs_5nlogn": round(p3.info["flops_5nlogn"] / (ms3 * 1e-3) / 1e9, 1),
+    }
+    p3.close()
+    del x3t, y3
     # real input (rdft): 8192 real signals of N = 2^12 (two per transform slot)
     xr = torch.from_numpy(workloads.normal(5, (8192, 4096)).real.astype(np.float32)).to(dev)
     rp = qft.RealPlan(12, 8192)
@@ -156,6 +170,55 @@ def extra_workloads(dev, stream):
     }
     rp.close()
     return out
+
+
+def config_errors(dev):
+    """Max relative RMS error (eq. qft_44 per signal) of the GPU result
+    against the FP64 oracle on the same (rounded) input, for every workload
+    configuration (c2 is reported with the main line)."""
+    import torch
+    import paper_1301_0763_amd as qft
+    import workloads
+    from oracle import build as OB
+    from oracle import direct as D
+    err = {}
+    x = workloads.make("c1")  # full O(N^2) definition
+    X = qft.fft(torch.from_numpy(x).to(dev)).cpu().numpy()
+    err["c1"] = float(f"{D.relative_l2(X, D.dft(x.astype(np.complex128))).max():.3e}")
+    x3, _, _ = workloads.make("c3")
+    X3 = qft.fft(torch.from_numpy(x3).to(dev)).cpu().numpy()
+    err["c3"] = float(f"{D.relative_l2(X3, OB.cdft(x3.astype(np.complex128))).max():.3e}")
+    del X3
+    r, vals = workloads.make("c4")
+    off = np.concatenate([[0], np.cumsum(1 << r.astype(np.int64))])
+    for name, dt in (("c4_fp32", qft.QFT_C32), ("c4_fp16_storage", qft.QFT_C16)):
+        if dt == qft.QFT_C16:
+            host = np.stack([vals.real, vals.imag], -1).astype(np.float16)
+            xin = host[..., 0].astype(np.float64) + 1j * host[..., 1].astype(np.float64)
+            t = torch.from_numpy(host).to(dev).view(torch.complex32).reshape(-1)
+            o = qft.fft_packed(t, r.tolist()).view(torch.float16).reshape(-1, 2).float()
+            got = o[:, 0].cpu().numpy() + 1j * o[:, 1].cpu().numpy()
+        else:
+            xin = vals.astype(np.complex128)
+            got = qft.fft_packed(torch.from_numpy(vals).to(dev), r.tolist()).cpu().numpy()
+        worst = 0.0
+        for lg in np.unique(r):
+            idx = np.nonzero(r == lg)[0]
+            N = 1 << int(lg)
+            xs = np.stack([xin[off[i]:off[i] + N] for i in idx])
+            gs = np.stack([got[off[i]:off[i] + N] for i in idx]).astype(np.complex128)
+            worst = max(worst, D.relative_l2(gs, OB.cdft(xs)).max())
+        err[name] = float(f"{worst:.3e}")
+    x5, _ = workloads.make("c5")
+    X5 = qft.fft(torch.from_numpy(x5).to(dev)).cpu().numpy()
+    err["c5_fwd"] = float(f"{D.relative_l2(X5, OB.cdft(x5.astype(np.complex128))).max():.3e}")
+    xr = workloads.normal(5, (64, 4096)).real.astype(np.float32)
+    H = qft.rdft(torch.from_numpy(xr).to(dev)).cpu().numpy()
+    ref = OB.cdft(xr.astype(np.complex128))[:, :2049]
+    err["rdft_N4096"] = float(f"{D.relative_l2(H, ref).max():.3e}")
+    err["target_fp32"] = "1e-5 * log2 N (c1 1.0e-4, c3 2.4e-4, c4 <= 1.4e-4, c5 1.2e-4)"
+    err["target_fp16_storage"] = "1e-3 (output rounding to FP16)"
+    return err
 
 
 def cpu_baseline(x, log2n, min_seconds=10.0):
@@ -294,6 +357,7 @@ def main():
                                        "target": 1e-5 * log2n}
     if not args.no_extra and wname == "c2":
         out.update(extra_workloads(dev, stream))
+        out["max_rel_error_vs_fp64_oracle"] = config_errors(dev)
     print(json.dumps(out))
     plan.close()
 
