@@ -1,11 +1,12 @@
 """Builds the gfx950 library ``libqft.so`` in-tree.
 
-Thirteen translation units compile in parallel (at most MAX_JOBS or one per
+Fifteen translation units compile in parallel (at most MAX_JOBS or one per
 CPU at a time) and link into one shared library: ``csrc/qft_lib.hip``
-(plans, C ABI, two-pass and multi-pass kernels) and ``csrc/qft_tiles.hip``
-once per storage type (``-DQFT_TILE_DT=0`` complex FP32, ``=1`` complex
-FP16), tile size (``-DQFT_TILE_TL=12, 13, 14``) and direction
-(``-DQFT_TILE_SWAP=0`` forward, ``=1`` adjoint).
+(plans, C ABI, two-pass kernels), ``csrc/qft_multipass.hip`` once per
+storage type (``-DQFT_MP_DT=0`` complex FP32, ``=1`` complex FP16) and
+``csrc/qft_tiles.hip`` once per storage type (``-DQFT_TILE_DT``), tile size
+(``-DQFT_TILE_TL=12, 13, 14``) and direction (``-DQFT_TILE_SWAP=0``
+forward, ``=1`` adjoint).
 
 Flags: ``--offload-arch=gfx950 -O3`` and packed FP32 instructions disabled
 (``-Xclang -target-feature -Xclang -packed-fp32-ops``; the host pass warns
@@ -20,7 +21,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SRC = os.path.join(CSRC, "qft_lib.hip")
 TILES = os.path.join(CSRC, "qft_tiles.hip")
-DEPS = [SRC, TILES] + [os.path.join(CSRC, f) for f in
+MULTI = os.path.join(CSRC, "qft_multipass.hip")
+DEPS = [SRC, TILES, MULTI] + [os.path.join(CSRC, f) for f in
                        ("qft_device.hpp", "qft_schedule.hpp", "qft_kernels.hpp")]
 LIB = os.path.join(HERE, "libqft.so")
 ROOT = os.path.dirname(HERE)
@@ -47,7 +49,8 @@ def build(verbose=False):
         units = [(TILES, ["-DQFT_TILE_DT=%d" % dt, "-DQFT_TILE_TL=%d" % tl,
                           "-DQFT_TILE_SWAP=%d" % sw], "tiles_%d_%d_%d.o" % (dt, tl, sw))
                  for tl in (14, 13, 12) for dt in (0, 1) for sw in (0, 1)]
-        units.insert(0, (SRC, [], "lib.o"))
+        units[0:0] = [(SRC, [], "lib.o")] + [
+            (MULTI, ["-DQFT_MP_DT=%d" % dt], "multipass_%d.o" % dt) for dt in (0, 1)]
         # at most one compiler per CPU (each takes ~1-2 GB)
         jobs = max(1, min(len(units), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
         msgs, failed, running, pending = [], False, [], list(units)

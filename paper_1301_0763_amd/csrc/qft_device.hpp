@@ -873,49 +873,11 @@ QFT_HD void tile_body(const typename Store<DT>::T* x, typename Store<DT>::T* X, 
 
 // ===========================================================================
 // Multi-pass path (one transform too large for a workgroup).  Work items of
-// the global passes over a heap buffer W of `batch` transforms.
+// the global passes over heap buffers of `batch` transforms (transform t at
+// cell t 2^logn, DCT side first, DST side at + N/2).
 // ===========================================================================
-// fold item i < batch * N/2
-template <int DT, bool SWAP, typename WP>
-QFT_HD void mp_fold_item(const typename Store<DT>::T* x, WP W, int logn, int64_t i) {
-  const int n = 1 << logn, h = n >> 1;
-  const int64_t t = i >> (logn - 1);
-  const int m = (int)(i & (h - 1));
-  const typename Store<DT>::T* xt = x + (t << logn);
-  auto w = W + (t << logn);
-  if (m == 0) {
-    w[0] = sw<SWAP>(Store<DT>::ld(xt, 0));
-    w[h] = sw<SWAP>(Store<DT>::ld(xt, h));
-  } else {
-    const float2 a = sw<SWAP>(Store<DT>::ld(xt, m));
-    const float2 b = sw<SWAP>(Store<DT>::ld(xt, n - m));
-    const int l = __builtin_ctz(m);
-    const int cell = (n >> (l + 2)) + (m >> (l + 1));
-    w[cell] = cadd(a, b);
-    w[h + cell] = csub(a, b);
-  }
-}
-
-// combine item i < batch * N/2
-template <int DT, bool SWAP, typename WP>
-QFT_HD void mp_combine_item(WP W, typename Store<DT>::T* X, int logn, int64_t i) {
-  const int n = 1 << logn, h = n >> 1;
-  const int64_t t = i >> (logn - 1);
-  const int k = (int)(i & (h - 1));
-  typename Store<DT>::T* Xt = X + (t << logn);
-  auto w = W + (t << logn);
-  if (k == 0) {
-    Store<DT>::st(Xt, 0, sw<SWAP>(w[0]));
-    Store<DT>::st(Xt, h, sw<SWAP>(w[h]));
-  } else {
-    const float2 C = w[k], S = w[h + k];
-    Store<DT>::st(Xt, k, sw<SWAP>(make_float2(C.x + S.y, C.y - S.x)));
-    Store<DT>::st(Xt, n - k, sw<SWAP>(make_float2(C.x - S.y, C.y + S.x)));
-  }
-}
-
-// Fold and combine items through a tile IO accessor (real-input plans):
-// item i < slots * N/2, transform slot t = i / (N/2).
+// Fold item i < batch * N/2 through an IO accessor (fetch + fold as in the
+// tile body), transform slot t = i / (N/2).
 template <class IO, typename WP>
 QFT_HD void mp_fold_io_item(const IO& io, WP W, int logn, int64_t i) {
   const int n = 1 << logn, h = n >> 1;
@@ -937,21 +899,6 @@ QFT_HD void mp_fold_io_item(const IO& io, WP W, int logn, int64_t i) {
   }
 }
 
-template <class IO, typename WP>
-QFT_HD void mp_combine_io_item(const IO& io, WP W, int logn, int64_t i) {
-  const int n = 1 << logn, h = n >> 1;
-  const int64_t t = i >> (logn - 1);
-  const int k = (int)(i & (h - 1));
-  auto w = W + (t << logn);
-  const auto o = io.out((int)t);
-  if (k == 0) {
-    io.put_edge(o, 0, w[0]);
-    io.put_edge(o, h, w[h]);
-  } else {
-    io.put(o, n, k, w[k], w[h + k]);
-  }
-}
-
 // forward group item i < 2*batch * 2^(logn-K-2): K rounds ending at
 // S = 2^(hi-K+1) >= 4, in place (groups are closed cell sets).
 template <int K, typename WP>
@@ -968,38 +915,39 @@ QFT_HD void mp_fwd_item(WP W, int logn, int hi, const float* sec, int64_t i) {
   else fwd_group<K, false>(sd, 1 << hi, j, x, sec, true);
 }
 
-// backward round S = 2^s, item i < 2*batch * N/4: Win -> Wout (cells [0, S)
-// of each side, which are no block of this round, are copied unchanged).
-template <typename RP, typename WP>
-QFT_HD void mp_bwd_item(RP Win, WP Wout, int logn, int s, int64_t i) {
+// K backward rounds S = 2^(s-K+1) .. 2^s on every side, Win -> Wout; item
+// i < 2*batch * 2^(logn-1-K).  With G = 2^(s-K), item (side, j, ii) of a
+// segment j >= 1 of S cells computes outputs ii 2^K .. ii 2^K + 2^K - 1 of
+// the segment (bwd_group_load).  The items of segment 0 take the side head:
+// cell ii of [0, G) unchanged (cell 0 of the DST side is the chain's top
+// cell) and the blocks M = G 2^a, a < K, which are complete after a more
+// rounds, 2^K outputs per item in both cases.
+template <int K, typename RP, typename WP>
+QFT_HD void mp_bwd_group_item(RP Win, WP Wout, int logn, int s, int64_t i) {
   const int lgside = logn - 1;
-  const int lgItems = lgside - 1;
-  const int S = 1 << s;
+  const int lgItems = lgside - K;
+  const int lgG = s - K;
   const int64_t si = i >> lgItems;
   const int item = (int)(i & ((1 << lgItems) - 1));
-  const int j = item >> (s - 1);
-  const int ii = item & ((S >> 1) - 1);
+  const int j = item >> lgG;
+  const int ii = item & ((1 << lgG) - 1);
   auto sin = Win + (si << lgside);
   auto sout = Wout + (si << lgside);
-  if (j == 0) {
-    sout[2 * ii] = sin[2 * ii];
-    sout[2 * ii + 1] = sin[2 * ii + 1];
+  if (j > 0) {
+    float2 y[1 << K];
+    if (si & 1) bwd_group_load<K, true>(sin, 1 << s, j, ii, y);
+    else bwd_group_load<K, false>(sin, 1 << s, j, ii, y);
+    const int o = (j << s) + (ii << K);
+#pragma unroll
+    for (int e = 0; e < (1 << K); ++e) sout[o + e] = y[e];
   } else {
-    float2 y0, y1;
-    if (si & 1) bwd_item<true>(sin, S, j, ii, y0, y1);
-    else bwd_item<false>(sin, S, j, ii, y0, y1);
-    sout[j * S + 2 * ii] = y0;
-    sout[j * S + 2 * ii + 1] = y1;
+    float2 hv[(1 << K) - 1];
+    const float2 c = sin[ii];
+    if (si & 1) bwd_head_load<K, true, 0>(sin, 1 << lgG, ii, hv);
+    else bwd_head_load<K, false, 0>(sin, 1 << lgG, ii, hv);
+    sout[ii] = c;
+    bwd_head_store<K, 0>(sout, 1 << lgG, ii, hv);
   }
-}
-
-// chain level P = 2^p, item i < batch * chain_groups(p), in place.
-template <typename WP>
-QFT_HD void mp_chain_item(WP W, int logn, int p, int64_t i) {
-  const int per_t = chain_groups(p);
-  const int64_t t = i / per_t;
-  const int g = (int)(i - t * per_t);
-  chain_item(W + (t << logn), logn, p, g);
 }
 
 // Segment pass, one workgroup: block r of transform heap wt (length 2^logn)
@@ -1651,6 +1599,24 @@ struct GatherIO : ComplexIO<DT, SWAP> {
   }
 };
 
+// Contiguous batch of transforms of a run-time length 2^logn (multi-pass).
+template <int DT, bool SWAP>
+struct ContigRtIO : ComplexIO<DT, SWAP> {
+  using E = typename Store<DT>::T;
+  using typename ComplexIO<DT, SWAP>::Raw;
+  const E* x;
+  E* X;
+  int logn;
+  QFT_HD ContigRtIO(const E* x_, E* X_, int lg) : x(x_), X(X_), logn(lg) {}
+  QFT_HD E* out(int t) const { return X + ((int64_t)t << logn); }
+  QFT_HD void fetch(int t, int m, Raw& r) const {
+    const int n = 1 << logn, h = n >> 1;
+    const E* xt = x + ((int64_t)t << logn);
+    r.a = this->load(xt, m);
+    r.b = this->load(xt, m == 0 ? h : n - m);
+  }
+};
+
 // Real-input transform (rdft, Sec. 4.2) of real signals 2t and 2t+1 of a
 // batch of `rows` signals of N = 2^LOGN points (row r at x + r N), as the
 // two lanes of transform t.  Output: the half spectrum X(k) = C(k) - i S(k),
@@ -1882,6 +1848,137 @@ QFT_HD void chain_fused(const Acc& acc, const IO& io, int Tact, int tid, Sync sy
   chain_passes<PBLK, PTOP, T, NT>(acc, tid, true, sync);
   if constexpr (COMBINE) chain_top_combine<PLOG, T, NT>(acc, io, Tact, tid);
   else chain_pass<(1 << PTOP), 3, T, NT>(acc, tid, true, sync);
+}
+
+// ---------------------------------------------------------------------------
+// Chain passes of the multi-pass path: levels P = 2^p .. 2^(p+K-1) (P >= 8)
+// with p known at run time.  Every index of a K-level group is a multiple of
+// P/4 plus 0 or +-k, so the groups of chain_generic / chain_special_load are
+// evaluated on the index sets of P = 4 scaled by u = P/4.  E values (cells
+// [0, P/4) of each side, E(P/4) in the top cell) come from one buffer, the
+// DCT-II / DST-II blocks from another.
+// ---------------------------------------------------------------------------
+template <int K, bool DST, typename EP, typename OP>
+QFT_HD void chain_generic_rt(EP se, OP so, int u, int k, float2* v) {
+  float2 o[1 << K];
+#pragma unroll
+  for (int l = 0; l < K; ++l) {
+#pragma unroll
+    for (int m = 0; m < (1 << l); ++m)
+      o[(1 << l) - 1 + m] =
+          so[((1 << l) + chain_c(4, l, m)) * u + chain_sgn(l, m) * k - (DST ? 1 : 0)];
+  }
+  v[0] = se[k];
+#pragma unroll
+  for (int l = 0; l < K; ++l) {
+#pragma unroll
+    for (int m = (1 << l) - 1; m >= 0; --m) {
+      const float2 E = v[m], O = o[(1 << l) - 1 + m];
+      v[2 * m] = cadd(E, O);
+      v[2 * m + 1] = DST ? csub(O, E) : csub(E, O);
+    }
+  }
+}
+
+template <int K, int L, bool DST, typename OP>
+QFT_HD void chain_special_levels_rt(OP so, int u, float2* v) {
+  if constexpr (L < K) {
+    constexpr ChainList cur = chain_special(4, L, DST);
+    constexpr ChainList nxt = chain_special(4, L + 1, DST);
+    constexpr int Qn = 4 << L;
+    float2 nv[(1 << K) + 1];
+    int pos = 0;
+#pragma unroll
+    for (int m = 0; m < cur.n; ++m) {
+      const int i = cur.idx[m];
+      if (DST || i < Qn / 4) {
+        const float2 E = v[m], O = so[(Qn / 4 + i) * u - (DST ? 1 : 0)];
+        nv[pos] = cadd(E, O);
+        nv[pos + 1] = DST ? csub(O, E) : csub(E, O);
+        pos += 2;
+      } else {
+        nv[pos] = v[m];
+        pos += 1;
+      }
+    }
+    if constexpr (DST) nv[nxt.n - 1] = so[(Qn / 2) * u - 1];  // S_Q(Q/4) = O(Q/4)
+#pragma unroll
+    for (int m = 0; m < nxt.n; ++m) v[m] = nv[m];
+    chain_special_levels_rt<K, L + 1, DST>(so, u, v);
+  }
+}
+
+// Loads and runs the K levels of group k of transform heap t: vc / vs get
+// the DCT and DST outputs (generic: 2^K each; k = 0: the lists of
+// chain_special(4, K, .), indices scaled by u).
+template <int K, typename EP, typename OP>
+QFT_HD void mp_chain_group(EP Et, OP Ot, int h, int u, int k, float2* vc, float2* vs) {
+  if (k == 0) {
+    vc[0] = Et[0];
+    vc[1] = Et[h];  // top cell
+    chain_special_levels_rt<K, 0, false>(Ot, u, vc);
+    chain_special_levels_rt<K, 0, true>(Ot + h, u, vs);
+  } else {
+    chain_generic_rt<K, false>(Et, Ot, u, k, vc);
+    chain_generic_rt<K, true>(Et + h, Ot + h, u, k, vs);
+  }
+}
+
+// Chain pass, item i < batch * P/4 = (transform t, group k): E from Ein,
+// blocks from Wo, outputs to Wout.  Ein == Wout is race free: group k reads
+// the E cells k (k = 0: cell 0 and the top cell) and writes cell k, the top
+// cell (k = 0) and cells >= P/4, which no other group reads.
+template <int K, typename EP, typename OP, typename WP>
+QFT_HD void mp_chain_item(EP Ein, OP Wo, WP Wout, int logn, int p, int64_t i) {
+  const int h = 1 << (logn - 1), u = 1 << (p - 2);
+  const int64_t b = (i >> (p - 2)) << logn;
+  const int k = (int)(i & (u - 1));
+  float2 vc[(1 << K) + 1], vs[(1 << K) + 1];
+  mp_chain_group<K>(Ein + b, Wo + b, h, u, k, vc, vs);
+  auto dc = Wout + b;
+  auto ds = Wout + b + h;
+  if (k == 0) {
+    constexpr ChainList fc = chain_special(4, K, false);
+    constexpr ChainList fs = chain_special(4, K, true);
+    constexpr int half = 1 << K;  // Q/2 of the last level, scaled
+#pragma unroll
+    for (int m = 0; m < fc.n; ++m) dc[fc.idx[m] == half ? h : fc.idx[m] * u] = vc[m];
+#pragma unroll
+    for (int m = 0; m < fs.n; ++m) ds[fs.idx[m] * u] = vs[m];
+  } else {
+#pragma unroll
+    for (int m = 0; m < (1 << K); ++m) {
+      const int c = chain_c(4, K, m) * u + chain_sgn(K, m) * k;
+      dc[c] = vc[m];
+      ds[c] = vs[m];
+    }
+  }
+}
+
+// Last chain pass (its top level is N) fused with the combine of Sec. 4.1:
+// C(k) and S(k) of one index meet in the DCT and the DST group of one item.
+template <int K, class IO, typename EP, typename OP>
+QFT_HD void mp_chain_combine_item(const IO& io, EP Ein, OP Wo, int logn, int p, int64_t i) {
+  const int n = 1 << logn, h = n >> 1, u = 1 << (p - 2);
+  const int64_t t = i >> (p - 2);
+  const int64_t b = t << logn;
+  const int k = (int)(i & (u - 1));
+  float2 vc[(1 << K) + 1], vs[(1 << K) + 1];
+  mp_chain_group<K>(Ein + b, Wo + b, h, u, k, vc, vs);
+  const auto o = io.out((int)t);
+  if (k == 0) {
+    constexpr ChainList fc = chain_special(4, K, false);
+    constexpr ChainPairing pr = chain_pairing(4, K);
+#pragma unroll
+    for (int m = 0; m < fc.n; ++m) {
+      if (pr.ms[m] < 0) io.put_edge(o, fc.idx[m] * u, vc[m]);  // k = 0, N/2
+      else io.put(o, n, fc.idx[m] * u, vc[m], vs[pr.ms[m]]);
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < (1 << K); ++m)
+      io.put(o, n, chain_c(4, K, m) * u + chain_sgn(K, m) * k, vc[m], vs[m]);
+  }
 }
 
 // Whole tile: T transforms of 2^LOGN points, NT threads (LOGN >= 1).

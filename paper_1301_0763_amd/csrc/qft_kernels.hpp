@@ -1,7 +1,7 @@
 // Definitions shared by the library's translation units: the device barrier
-// functors and LDS layout constants of the kernels, and the launch interface
-// of the persistent tile kernels (built once per storage type in
-// qft_tiles.hip, called from the plan code in qft_lib.hip).
+// functors and LDS layout constants of the kernels, and the launch interfaces
+// of the persistent tile kernels (qft_tiles.hip) and of the multi-pass path
+// (qft_multipass.hip), called from the plan code in qft_lib.hip.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -76,5 +76,20 @@ hipError_t launch_tiles(const TileGroup& g, const void* in, void* out, const flo
 template <int DT, int TL>
 hipError_t launch_real(const TileGroup& g, int kind, const RealArgs& a, const float* sec,
                        hipStream_t st);
+
+// Multi-pass path (qft_multipass.hip, one translation unit per storage type
+// DT): `batch` contiguous transforms of 2^log2n points, kMpSegLog2 + 3 <=
+// log2n <= 24 (swap: the adjoint), or `rows` real signals of a real-input
+// plan (kind as in launch_real; two signals per transform slot).  W0 and
+// W1 are heap buffers of (transforms or slots) * 2^log2n cells each.
+constexpr int kMpSegLog2 = 12;  // LDS segment of the multi-pass path
+
+template <int DT>
+hipError_t launch_multipass(bool swap, const void* in, void* out, int log2n, int64_t batch,
+                            const float* sec, float2* W0, float2* W1, hipStream_t st);
+
+template <int DT>
+hipError_t launch_multipass_real(int kind, const RealArgs& a, int log2n, int64_t rows,
+                                 const float* sec, float2* W0, float2* W1, hipStream_t st);
 
 }  // namespace qftk

@@ -1,7 +1,7 @@
-// Improved-QFT DFT library for gfx950: plans, schedules, the multi-pass and
-// two-pass kernels, and the C ABI of include/qft.h.  The cell layout and the
-// formula of every step are in qft_device.hpp; the persistent tile kernels
-// (N <= 2^14) are in qft_tiles.hip.
+// Improved-QFT DFT library for gfx950: plans, schedules, the two-pass
+// kernels, and the C ABI of include/qft.h.  The cell layout and the formula
+// of every step are in qft_device.hpp; the persistent tile kernels (N <=
+// 2^14) are in qft_tiles.hip, the multi-pass path in qft_multipass.hip.
 //
 // Execution paths
 //  * persistent tile kernel (N <= 2^14): a workgroup holds whole transforms
@@ -13,9 +13,10 @@
 //    streams the top backward round, the last two chain levels and the
 //    combine.
 //  * multi-pass path (N > 2^16): fold into a global heap buffer, forward
-//    rounds of the blocks larger than one 2^12-cell segment in global
-//    memory, one LDS pass per segment, backward rounds and chain levels of
-//    the large blocks in global memory, combine.
+//    rounds of the blocks larger than one 2^12-cell segment (up to five per
+//    pass, in registers), one LDS pass per segment, backward rounds and
+//    chain levels of the large blocks (up to five per pass), the last chain
+//    pass writing X.
 // A plan holds one or more schedules (which transform sizes run in which
 // tile-size group); qft_plan_autotune times them and keeps the fastest.
 #include <hip/hip_runtime.h>
@@ -33,71 +34,6 @@
 #include "../../include/qft.h"
 
 namespace qftk {
-
-constexpr int MP_BLOCK = 256;
-
-#define QFT_GRID_STRIDE(i, total)                                              \
-  for (int64_t i = (int64_t)blockIdx.x * MP_BLOCK + threadIdx.x; i < (total); \
-       i += (int64_t)gridDim.x * MP_BLOCK)
-
-template <int DT, bool SWAP>
-__global__ __launch_bounds__(MP_BLOCK) void mp_fold_kernel(const typename Store<DT>::T* x,
-                                                           float2* W, int logn, int64_t batch) {
-  QFT_GRID_STRIDE(i, batch << (logn - 1)) mp_fold_item<DT, SWAP>(x, W, logn, i);
-}
-
-template <int DT, bool SWAP>
-__global__ __launch_bounds__(MP_BLOCK) void mp_combine_kernel(const float2* W,
-                                                              typename Store<DT>::T* X,
-                                                              int logn, int64_t batch) {
-  QFT_GRID_STRIDE(i, batch << (logn - 1)) mp_combine_item<DT, SWAP>(W, X, logn, i);
-}
-
-template <int K>
-__global__ __launch_bounds__(MP_BLOCK) void mp_fwd_kernel(float2* W, int logn, int64_t batch,
-                                                          int hi, const float* sec) {
-  QFT_GRID_STRIDE(i, (2 * batch) << (logn - K - 2)) mp_fwd_item<K>(W, logn, hi, sec, i);
-}
-
-__global__ __launch_bounds__(MP_BLOCK) void mp_bwd_kernel(const float2* Win, float2* Wout,
-                                                          int logn, int64_t batch, int s) {
-  QFT_GRID_STRIDE(i, (2 * batch) << (logn - 2)) mp_bwd_item(Win, Wout, logn, s, i);
-}
-
-__global__ __launch_bounds__(MP_BLOCK) void mp_chain_kernel(float2* W, int logn, int64_t batch,
-                                                            int p) {
-  QFT_GRID_STRIDE(i, batch * chain_groups(p)) mp_chain_item(W, logn, p, i);
-}
-
-// Multi-pass fold and combine of real-input plans (IO = RealPairIO or
-// DctDstIO with the length given at run time).
-template <class IO>
-__global__ __launch_bounds__(MP_BLOCK) void mp_fold_io_kernel(IO io, float2* W, int logn,
-                                                              int64_t slots) {
-  QFT_GRID_STRIDE(i, slots << (logn - 1)) mp_fold_io_item(io, W, logn, i);
-}
-
-template <class IO>
-__global__ __launch_bounds__(MP_BLOCK) void mp_combine_io_kernel(IO io, const float2* W,
-                                                                 int logn, int64_t slots) {
-  QFT_GRID_STRIDE(i, slots << (logn - 1)) mp_combine_io_item(io, W, logn, i);
-}
-
-#undef QFT_GRID_STRIDE
-
-template <int MC_LOG2, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void mp_segment_kernel(float2* W, int logn,
-                                                           const float* sec) {
-  constexpr int MC = 1 << MC_LOG2;
-  constexpr int CPT = (2 * MC) / BLOCK;
-  __shared__ float2 Ll[padded_cells<kPad>(2 * MC)];
-  const PadPtr<kPad> L{Ll, 0};
-  const int per_t = mp_segment_blocks(logn, MC_LOG2);
-  const int64_t t = blockIdx.x / per_t;
-  const int r = (int)(blockIdx.x - t * per_t);
-  mp_segment_body<MC_LOG2, CPT>(W + (t << logn), L, logn, r, sec, (int)threadIdx.x, BLOCK, kWave,
-                                DevSync{}, DevWaveSync{});
-}
 
 // Two-pass path, N = 8 * 2^MC_LOG2.  Pass A: both sides of one segment per
 // workgroup, 4 workgroups per transform; block b serves transform
@@ -140,8 +76,6 @@ __global__ __launch_bounds__(256) void tp_b_kernel(const float2* W, typename Sto
 namespace {
 
 thread_local int g_last_hip_error = 0;
-
-constexpr int kSegLog2 = 12;  // multi-pass segment size
 
 // Transforms handled outside the tile groups (N > 2^14): `batch` contiguous
 // transforms of 2^log2n points starting at element `offset`.
@@ -301,111 +235,6 @@ inline unsigned grid_for(int64_t work, int block) {
   return (unsigned)g;
 }
 
-// GPU executor of the multi-pass schedule (qft_schedule.hpp).
-template <int DT, bool SWAP>
-struct GpuMultipass {
-  using T = typename qftk::Store<DT>::T;
-  const T* x;
-  T* X;
-  int logn;
-  int64_t batch;
-  const float* sec;
-  float2* cur;
-  float2* oth;
-  hipStream_t st;
-  unsigned g_elem() const { return grid_for(batch << (logn - 1), qftk::MP_BLOCK); }
-  void fold() {
-    hipLaunchKernelGGL((qftk::mp_fold_kernel<DT, SWAP>), dim3(g_elem()), dim3(qftk::MP_BLOCK), 0,
-                       st, x, cur, logn, batch);
-  }
-  void fwd(int K, int hi) {
-    const unsigned g = grid_for((2 * batch) << (logn - K - 2), qftk::MP_BLOCK);
-    if (K == 3)
-      hipLaunchKernelGGL((qftk::mp_fwd_kernel<3>), dim3(g), dim3(qftk::MP_BLOCK), 0, st, cur, logn,
-                         batch, hi, sec);
-    else if (K == 2)
-      hipLaunchKernelGGL((qftk::mp_fwd_kernel<2>), dim3(g), dim3(qftk::MP_BLOCK), 0, st, cur, logn,
-                         batch, hi, sec);
-    else
-      hipLaunchKernelGGL((qftk::mp_fwd_kernel<1>), dim3(g), dim3(qftk::MP_BLOCK), 0, st, cur, logn,
-                         batch, hi, sec);
-  }
-  void segment() {
-    const int64_t blocks = batch * qftk::mp_segment_blocks(logn, kSegLog2);
-    hipLaunchKernelGGL((qftk::mp_segment_kernel<kSegLog2, 256>), dim3((unsigned)blocks), dim3(256),
-                       0, st, cur, logn, sec);
-  }
-  void bwd(int s) {
-    hipLaunchKernelGGL(qftk::mp_bwd_kernel, dim3(g_elem()), dim3(qftk::MP_BLOCK), 0, st,
-                       (const float2*)cur, oth, logn, batch, s);
-    std::swap(cur, oth);
-  }
-  void chain(int p) {
-    hipLaunchKernelGGL(qftk::mp_chain_kernel,
-                       dim3(grid_for(batch * qftk::chain_groups(p), qftk::MP_BLOCK)),
-                       dim3(qftk::MP_BLOCK), 0, st, cur, logn, batch, p);
-  }
-  void combine() {
-    hipLaunchKernelGGL((qftk::mp_combine_kernel<DT, SWAP>), dim3(g_elem()), dim3(qftk::MP_BLOCK),
-                       0, st, (const float2*)cur, X, logn, batch);
-  }
-};
-
-template <int DT, bool SWAP>
-qft_status launch_multipass(const void* in, void* out, int log2n, int64_t batch,
-                            const float* sec, float2* W0, float2* W1, hipStream_t st) {
-  using T = typename qftk::Store<DT>::T;
-  if (batch * qftk::mp_segment_blocks(log2n, kSegLog2) > 0x7fffffff) return QFT_ERROR_INVALID_VALUE;
-  GpuMultipass<DT, SWAP> ex{(const T*)in, (T*)out, log2n, batch, sec, W0, W1, st};
-  qftk::multipass_schedule(ex, log2n, kSegLog2);
-  hipError_t e = hipGetLastError();
-  return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
-}
-
-// Multi-pass executor of a real-input plan: the real fold / combine through
-// the plan's IO accessor, the middle kernels of the complex path on the
-// transform slots (two real signals each).
-template <class IO>
-struct GpuMultipassReal {
-  GpuMultipass<0, false> mid;
-  IO io;
-  void fold() {
-    hipLaunchKernelGGL((qftk::mp_fold_io_kernel<IO>), dim3(mid.g_elem()), dim3(qftk::MP_BLOCK),
-                       0, mid.st, io, mid.cur, mid.logn, mid.batch);
-  }
-  void fwd(int K, int hi) { mid.fwd(K, hi); }
-  void segment() { mid.segment(); }
-  void bwd(int s) { mid.bwd(s); }
-  void chain(int p) { mid.chain(p); }
-  void combine() {
-    hipLaunchKernelGGL((qftk::mp_combine_io_kernel<IO>), dim3(mid.g_elem()),
-                       dim3(qftk::MP_BLOCK), 0, mid.st, io, (const float2*)mid.cur, mid.logn,
-                       mid.batch);
-  }
-};
-
-template <int DT>
-qft_status launch_multipass_real(int kind, const qftk::RealArgs& a, int log2n, int64_t rows,
-                                 const float* sec, float2* W0, float2* W1, hipStream_t st) {
-  using R = typename qftk::RStore<DT>::T;
-  using E = typename qftk::Store<DT>::T;
-  const int64_t slots = (rows + 1) / 2;
-  if (slots * qftk::mp_segment_blocks(log2n, kSegLog2) > 0x7fffffff) return QFT_ERROR_INVALID_VALUE;
-  const GpuMultipass<0, false> mid{nullptr, nullptr, log2n, slots, sec, W0, W1, st};
-  if (kind == 0) {
-    const qftk::RealPairIO<DT, 0> io{(const R*)a.in0, (E*)a.out0, rows, log2n};
-    GpuMultipassReal<qftk::RealPairIO<DT, 0>> ex{mid, io};
-    qftk::multipass_schedule(ex, log2n, kSegLog2);
-  } else {
-    const qftk::DctDstIO<DT, 0> io{(const R*)a.in0, (const R*)a.in1, (R*)a.out0, (R*)a.out1,
-                                   rows, log2n};
-    GpuMultipassReal<qftk::DctDstIO<DT, 0>> ex{mid, io};
-    qftk::multipass_schedule(ex, log2n, kSegLog2);
-  }
-  hipError_t e = hipGetLastError();
-  return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
-}
-
 // Two-pass path (N = 2^15, 2^16): pass A into the heap buffer W, pass B to X.
 template <int DT, bool SWAP>
 qft_status launch_twopass(const void* in, void* out, int log2n, int64_t batch, const float* sec,
@@ -437,7 +266,8 @@ qft_status launch_large(const void* in, void* out, int log2n, int64_t batch, con
                         float2* W0, float2* W1, hipStream_t st) {
   if (log2n == 15 || log2n == 16)
     return launch_twopass<DT, SWAP>(in, out, log2n, batch, sec, W0, st);
-  return launch_multipass<DT, SWAP>(in, out, log2n, batch, sec, W0, W1, st);
+  const hipError_t e = qftk::launch_multipass<DT>(SWAP, in, out, log2n, batch, sec, W0, W1, st);
+  return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
 }
 
 template <int DT, bool SWAP>
@@ -504,9 +334,11 @@ qft_status run_real(const qft_plan_s* p, int kind, const qftk::RealArgs& a, hipS
   if (p->log2n > qftk::kMaxTileLog2) {
     float2* W0 = p->d_work;
     float2* W1 = p->d_work + p->work_cells;
-    return p->dtype == QFT_C16
-               ? launch_multipass_real<1>(kind, a, p->log2n, p->batch, p->d_sec, W0, W1, st)
-               : launch_multipass_real<0>(kind, a, p->log2n, p->batch, p->d_sec, W0, W1, st);
+    const hipError_t e =
+        p->dtype == QFT_C16
+            ? qftk::launch_multipass_real<1>(kind, a, p->log2n, p->batch, p->d_sec, W0, W1, st)
+            : qftk::launch_multipass_real<0>(kind, a, p->log2n, p->batch, p->d_sec, W0, W1, st);
+    return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
   }
   const qftk::TileGroup& g = p->schedules[p->chosen].groups[0];
   hipError_t e = hipErrorInvalidValue;

@@ -27,38 +27,60 @@ inline void fill_secants(float* out, int log2n_max) {
   }
 }
 
+// Splits R >= 1 consecutive levels into ceil(R / kmax) chunks whose sizes
+// differ by at most one (larger chunks first); returns the chunk count.
+inline int level_chunks(int R, int kmax, int* sizes) {
+  const int n = (R + kmax - 1) / kmax;
+  for (int c = 0; c < n; ++c) sizes[c] = R / n + (c < R % n ? 1 : 0);
+  return n;
+}
+
+// Most levels of one global pass (forward rounds, backward rounds, chain
+// levels), at most 5 each.  Forward passes of 5 rounds hold 64 cells per
+// thread (256 VGPRs, two waves per SIMD) and stream slower than a 4-round
+// and a 3-round pass together; 5 backward rounds or chain levels per pass
+// are faster than 4.
+struct MpLevels {
+  int fwd = 4, bwd = 5, chain = 5;
+};
+
 // Multi-pass schedule for transforms of length 2^logn that do not fit one
 // workgroup, with LDS segments of 2^seg_log2 cells (logn >= seg_log2 + 3).
-// `ex` provides: fold(), fwd(K, hi), segment(), bwd(s) (returns nothing; the
-// executor swaps its ping-pong buffers), chain(p), combine().
+// `ex` provides:
 //
-//   fold                 x -> heap buffer (real fold, Sec. 4.2)
-//   fwd(K, hi)           forward rounds S = 2^hi .. 2^(hi-K+1) on the blocks
-//                        longer than one segment (rounds S > 2^seg_log2)
-//   segment              every 2^seg_log2 segment: its remaining forward
+//   fold()               x -> heap buffer (real fold, Sec. 4.2)
+//   fwd(K, hi)           forward rounds S = 2^hi .. 2^(hi-K+1) of the blocks
+//                        longer than one segment, in place
+//   segment()            every 2^seg_log2 segment: its remaining forward
 //                        rounds and its backward rounds in LDS; the core
 //                        (both side heads) also runs the chain to
 //                        P = 2^(seg_log2+1)
-//   bwd(s)               backward round S = 2^s > 2^seg_log2
-//   chain(p)             chain level P = 2^p > 2^(seg_log2+1)
-//   combine              heap buffer -> X (Sec. 4.1 combine)
+//   bwd(K, hi)           backward rounds S = 2^(hi-K+1) .. 2^hi, from the
+//                        current heap buffer into the other one (the
+//                        executor swaps them)
+//   chain(K, p, first)   chain levels 2^p .. 2^(p+K-1): E values from the
+//                        heap buffer (first pass) or the chain buffer (the
+//                        other one), blocks from the heap buffer, outputs to
+//                        the chain buffer
+//   combine(K, p, first) the last chain levels (up to N) with the combine
+//                        of Sec. 4.1, outputs to X
+//
+// Each pass runs at most `lv` rounds or levels in registers.
 template <class Exec>
-void multipass_schedule(Exec& ex, int logn, int seg_log2) {
+void multipass_schedule(Exec& ex, int logn, int seg_log2, MpLevels lv = MpLevels{}) {
+  int sz[32];
   ex.fold();
   const int top = logn - 2, bottom = seg_log2 + 1;
-  if (top >= bottom) {
-    const int R = top - bottom + 1;
-    const int nch = (R + 2) / 3;
-    for (int c = nch - 1; c >= 0; --c) {
-      const int lo = bottom + 3 * c;
-      const int hi = std::min(top, lo + 2);
-      ex.fwd(hi - lo + 1, hi);
-    }
-  }
+  const int nf = level_chunks(top - bottom + 1, lv.fwd, sz);
+  for (int c = 0, hi = top; c < nf; hi -= sz[c], ++c) ex.fwd(sz[c], hi);
   ex.segment();
-  for (int s = seg_log2 + 1; s <= logn - 2; ++s) ex.bwd(s);
-  for (int p = seg_log2 + 2; p <= logn; ++p) ex.chain(p);
-  ex.combine();
+  const int nb = level_chunks(top - bottom + 1, lv.bwd, sz);
+  for (int c = nb - 1, lo = bottom; c >= 0; lo += sz[c], --c) ex.bwd(sz[c], lo + sz[c] - 1);
+  const int nc = level_chunks(logn - seg_log2 - 1, lv.chain, sz);
+  for (int c = 0, p = seg_log2 + 2; c < nc; p += sz[c], ++c) {
+    if (c + 1 < nc) ex.chain(sz[c], p, c == 0);
+    else ex.combine(sz[c], p, c == 0);
+  }
 }
 
 struct TileDesc {

@@ -239,11 +239,11 @@ std::vector<float> secants(int lg) {
   return s;
 }
 
-template <int DT, bool SWAP>
+// CPU executor of the multi-pass schedule: every pass runs its work items
+// one after another through the tracked pointers, one phase per pass.
+template <class IO>
 struct EmuMultipass {
-  using E = typename qftk::Store<DT>::T;
-  const E* x;
-  E* X;
+  IO io;
   int logn;
   int64_t batch;
   int seg_log2;
@@ -254,8 +254,6 @@ struct EmuMultipass {
   int64_t cells;
   Tracker gtr{1};
   int64_t races = 0;
-  // real-input plans: fold and combine through an IO accessor instead
-  std::function<void(TPtr, int64_t)> fold_io, combine_io;
   template <class F>
   void items(int64_t total, F f) {
     tl_slot = 0;
@@ -267,17 +265,22 @@ struct EmuMultipass {
   }
   TPtr G(float2* p) { return TPtr{p, 0, &gtr, cells}; }
   void fold() {
-    if (fold_io) {
-      items(batch << (logn - 1), [&](int64_t i) { fold_io(G(cur), i); });
-      return;
-    }
-    items(batch << (logn - 1), [&](int64_t i) { qftk::mp_fold_item<DT, SWAP>(x, G(cur), logn, i); });
+    items(batch << (logn - 1), [&](int64_t i) { qftk::mp_fold_io_item(io, G(cur), logn, i); });
+  }
+  template <int K>
+  void fwd_k(int hi) {
+    items((2 * batch) << (logn - K - 2),
+          [&](int64_t i) { qftk::mp_fwd_item<K>(G(cur), logn, hi, sec, i); });
   }
   void fwd(int K, int hi) {
-    const int64_t total = (2 * batch) << (logn - K - 2);
-    if (K == 3) items(total, [&](int64_t i) { qftk::mp_fwd_item<3>(G(cur), logn, hi, sec, i); });
-    else if (K == 2) items(total, [&](int64_t i) { qftk::mp_fwd_item<2>(G(cur), logn, hi, sec, i); });
-    else items(total, [&](int64_t i) { qftk::mp_fwd_item<1>(G(cur), logn, hi, sec, i); });
+    switch (K) {
+      case 1: fwd_k<1>(hi); break;
+      case 2: fwd_k<2>(hi); break;
+      case 3: fwd_k<3>(hi); break;
+      case 4: fwd_k<4>(hi); break;
+      case 5: fwd_k<5>(hi); break;
+      default: races = -1000000; break;
+    }
   }
   template <int MC_LOG2>
   void segment_mc() {
@@ -310,34 +313,74 @@ struct EmuMultipass {
       default: races = -1000000; break;
     }
   }
-  void bwd(int s) {
-    items((2 * batch) << (logn - 2),
-          [&](int64_t i) { qftk::mp_bwd_item(G(cur), G(oth), logn, s, i); });
+  template <int K>
+  void bwd_k(int hi) {
+    items((2 * batch) << (logn - 1 - K),
+          [&](int64_t i) { qftk::mp_bwd_group_item<K>(G(cur), G(oth), logn, hi, i); });
     std::swap(cur, oth);
   }
-  void chain(int p) {
-    items(batch * qftk::chain_groups(p), [&](int64_t i) { qftk::mp_chain_item(G(cur), logn, p, i); });
-  }
-  void combine() {
-    if (combine_io) {
-      items(batch << (logn - 1), [&](int64_t i) { combine_io(G(cur), i); });
-      return;
+  void bwd(int K, int hi) {
+    switch (K) {
+      case 1: bwd_k<1>(hi); break;
+      case 2: bwd_k<2>(hi); break;
+      case 3: bwd_k<3>(hi); break;
+      case 4: bwd_k<4>(hi); break;
+      case 5: bwd_k<5>(hi); break;
+      default: races = -1000000; break;
     }
-    items(batch << (logn - 1), [&](int64_t i) { qftk::mp_combine_item<DT, SWAP>(G(cur), X, logn, i); });
+  }
+  template <int K>
+  void chain_k(int p, bool first) {
+    float2* e = first ? cur : oth;
+    items(batch << (p - 2),
+          [&](int64_t i) { qftk::mp_chain_item<K>(G(e), G(cur), G(oth), logn, p, i); });
+  }
+  void chain(int K, int p, bool first) {
+    switch (K) {
+      case 1: chain_k<1>(p, first); break;
+      case 2: chain_k<2>(p, first); break;
+      case 3: chain_k<3>(p, first); break;
+      case 4: chain_k<4>(p, first); break;
+      case 5: chain_k<5>(p, first); break;
+      default: races = -1000000; break;
+    }
+  }
+  template <int K>
+  void combine_k(int p, bool first) {
+    float2* e = first ? cur : oth;
+    items(batch << (p - 2),
+          [&](int64_t i) { qftk::mp_chain_combine_item<K>(io, G(e), G(cur), logn, p, i); });
+  }
+  void combine(int K, int p, bool first) {
+    switch (K) {
+      case 1: combine_k<1>(p, first); break;
+      case 2: combine_k<2>(p, first); break;
+      case 3: combine_k<3>(p, first); break;
+      case 4: combine_k<4>(p, first); break;
+      case 5: combine_k<5>(p, first); break;
+      default: races = -1000000; break;
+    }
   }
 };
+
+template <class IO>
+int run_multipass(const IO& io, int logn, int64_t batch, int seg_log2, int nthr,
+                  const float* sec) {
+  std::vector<float2> w0((size_t)batch << logn), w1((size_t)batch << logn);
+  EmuMultipass<IO> ex{io, logn, batch, seg_log2, nthr, sec, w0.data(), w1.data(),
+                      (int64_t)batch << logn};
+  qftk::multipass_schedule(ex, logn, seg_log2);
+  if (ex.races < 0 || ex.gtr.oob) return -4;
+  return (int)(ex.races + ex.gtr.races);
+}
 
 template <int DT, bool SWAP>
 int multipass_impl(const void* x, void* X, int logn, int64_t batch, int seg_log2, int nthr,
                    const float* sec) {
   using E = typename qftk::Store<DT>::T;
   if (logn < seg_log2 + 3) return -3;
-  std::vector<float2> w0((size_t)batch << logn), w1((size_t)batch << logn);
-  EmuMultipass<DT, SWAP> ex{(const E*)x, (E*)X, logn, batch, seg_log2, nthr, sec,
-                            w0.data(), w1.data(), (int64_t)batch << logn};
-  qftk::multipass_schedule(ex, logn, seg_log2);
-  if (ex.races < 0 || ex.gtr.oob) return -4;
-  return (int)(ex.races + ex.gtr.races);
+  return run_multipass(qftk::ContigRtIO<DT, SWAP>((const E*)x, (E*)X, logn), logn, batch,
+                       seg_log2, nthr, sec);
 }
 
 // Multi-pass path of a real-input plan (kind 0: rdft, 1: DCT-0/DST-0).
@@ -348,21 +391,12 @@ int multipass_real_impl(int kind, int logn, int64_t rows, const void* in0, const
   using E = typename qftk::Store<DT>::T;
   if (logn < seg_log2 + 3) return -3;
   const int64_t slots = (rows + 1) / 2;
-  std::vector<float2> w0((size_t)slots << logn), w1((size_t)slots << logn);
-  EmuMultipass<DT, false> ex{nullptr, nullptr, logn, slots, seg_log2, nthr, sec,
-                             w0.data(), w1.data(), (int64_t)slots << logn};
-  const qftk::RealPairIO<DT, 0> rio{(const R*)in0, (E*)out0, rows, logn};
-  const qftk::DctDstIO<DT, 0> dio{(const R*)in0, (const R*)in1, (R*)out0, (R*)out1, rows, logn};
-  if (kind == 0) {
-    ex.fold_io = [&](TPtr W, int64_t i) { qftk::mp_fold_io_item(rio, W, logn, i); };
-    ex.combine_io = [&](TPtr W, int64_t i) { qftk::mp_combine_io_item(rio, W, logn, i); };
-  } else {
-    ex.fold_io = [&](TPtr W, int64_t i) { qftk::mp_fold_io_item(dio, W, logn, i); };
-    ex.combine_io = [&](TPtr W, int64_t i) { qftk::mp_combine_io_item(dio, W, logn, i); };
-  }
-  qftk::multipass_schedule(ex, logn, seg_log2);
-  if (ex.races < 0 || ex.gtr.oob) return -4;
-  return (int)(ex.races + ex.gtr.races);
+  if (kind == 0)
+    return run_multipass(qftk::RealPairIO<DT, 0>{(const R*)in0, (E*)out0, rows, logn}, logn,
+                         slots, seg_log2, nthr, sec);
+  return run_multipass(
+      qftk::DctDstIO<DT, 0>{(const R*)in0, (const R*)in1, (R*)out0, (R*)out1, rows, logn}, logn,
+      slots, seg_log2, nthr, sec);
 }
 
 template <int DT, bool SWAP>

@@ -105,11 +105,14 @@ def run_mp(emu, x, seg, nthr=16, swap=0):
 
 
 @pytest.mark.parametrize("seg,logn", [(3, 6), (3, 9), (4, 7), (4, 11), (5, 8), (5, 12),
-                                      (3, 12)])
+                                      (3, 12), (4, 13), (3, 14)])
 def test_multipass_small_segments(emu, seg, logn):
     """The multi-pass schedule with segments of 2^seg cells (the library uses
     2^12), so that the global forward/backward rounds and chain levels occur
-    at small N."""
+    at small N; the cases cover passes of 1 to 5 rounds or chain levels, one
+    to three chain passes, and the race tracker checks that the in-place
+    chain passes and the grouped backward passes touch no cell another item
+    of the same pass writes."""
     x = workloads.normal(seg * 100 + logn, (2, 1 << logn))
     races, out = run_mp(emu, x, seg)
     assert races == 0

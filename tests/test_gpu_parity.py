@@ -65,15 +65,18 @@ def test_all_tile_sizes(logn):
     assert err.max() <= tol(logn), err.max()
 
 
-@pytest.mark.parametrize("logn,B", [(15, 3), (16, 2), (17, 1), (18, 1)])
+@pytest.mark.parametrize("logn,B", [(15, 3), (16, 2), (17, 2), (18, 1), (19, 1), (20, 2),
+                                    (21, 1), (22, 1), (23, 1)])
 def test_multipass_sizes(logn, B):
+    """Two-pass (2^15, 2^16) and multi-pass sizes: every split of the global
+    rounds and chain levels into passes of 3 to 5 that the library uses."""
     say(f"multi-pass: N=2^{logn} B={B}")
     x = workloads.normal(2000 + logn, (B, 1 << logn))
     err = D.relative_l2(gpu_fwd(x), ref_fwd(x))
     assert err.max() <= tol(logn), err.max()
 
 
-@pytest.mark.parametrize("logn,B", [(3, 4), (10, 6), (14, 2), (16, 2)])
+@pytest.mark.parametrize("logn,B", [(3, 4), (10, 6), (14, 2), (16, 2), (20, 1)])
 def test_adjoint_and_round_trip(logn, B):
     say(f"adjoint: N=2^{logn} B={B}")
     x = workloads.uniform(3000 + logn, (B, 1 << logn))
