@@ -336,6 +336,41 @@ QFT_HD constexpr int padded_cells(int cells) {
   return PS >= 16 ? cells : cells + (cells >> PS);
 }
 
+// Row of a buffer at cell a, with the address arithmetic of the padding done
+// once: r[k] is cell a + k for k a multiple of 2^PS (the padding inside
+// [a, a + k) is k >> PS cells wherever a lies), r.run(e) is cell a + e for
+// the cells of a's own 2^PS-cell block (no padding in between).  Buffers
+// without padding (global memory) get the plain offset pointer.
+template <int PS>
+struct PadRow {
+  float2* p;
+  QFT_HD float2& operator[](int k) const { return p[PS >= 16 ? k : k + (k >> (PS & 15))]; }
+  QFT_HD float2& run(int e) const { return p[e]; }
+};
+
+// Callers index rows with multiples of 8 cells (the padding block may not be
+// larger) and anchor them at cells >= 0 of the buffer.
+constexpr int kMaxRowPad = 3;
+
+template <int PS>
+QFT_HD PadRow<PS> pad_row(const PadPtr<PS>& sd, int a) {
+  static_assert(PS >= 16 || PS <= kMaxRowPad, "row offsets are multiples of 8 cells");
+  const int c = sd.off + a;
+  return PadRow<PS>{sd.base + (PS >= 16 ? c : c + (c >> (PS & 15)))};
+}
+
+template <typename SP>
+struct PlainRow {
+  SP p;
+  QFT_HD decltype(auto) operator[](int k) const { return p[k]; }
+  QFT_HD decltype(auto) run(int e) const { return p[e]; }
+};
+
+template <typename SP>
+QFT_HD PlainRow<SP> pad_row(const SP& sd, int a) {
+  return PlainRow<SP>{sd + a};
+}
+
 // ---------------------------------------------------------------------------
 // Fused innermost rounds: forward rounds S = 2^K .. 2 and then backward
 // rounds S = 2 .. 2^K on the whole segment j of 2^K cells, in registers.
@@ -409,19 +444,9 @@ QFT_HD void tail_group(SP sd, int j, const float* __restrict__ sec, bool skip0) 
 // (DCT) or i-1 (DST), so it is loaded, not recomputed: 2^(K+1) - 1 loads,
 // K 2^(K-1) additions, no redundant arithmetic.
 // ---------------------------------------------------------------------------
-template <int K, bool DST, typename SP>
-QFT_HD void bwd_group_load(SP sd, int S, int j, int i, float2 (&y)[1 << K]) {
+template <int K, bool DST>
+QFT_HD void bwd_group_levels(float2 (&cur)[1 << K], float2 (&halo)[1 << K], float2 (&y)[1 << K]) {
   constexpr int R = 1 << K;
-  const int G = S >> K;
-  const int base = j * S;
-  float2 cur[R], halo[R];
-#pragma unroll
-  for (int c = 0; c < R; ++c) cur[c] = sd[base + c * G + i];
-  const bool has = DST ? (i >= 1) : (i + 1 < G);
-  const int hi = DST ? i - 1 : i + 1;
-#pragma unroll
-  for (int c = 0; c < R; ++c)
-    halo[c] = (c > 0 && has) ? (float2)sd[base + c * G + hi] : make_float2(0.f, 0.f);
 #pragma unroll
   for (int m = 1; m <= K; ++m) {
     const int len = 1 << m, hl = len >> 1;  // values per segment at level m / m-1
@@ -451,6 +476,39 @@ QFT_HD void bwd_group_load(SP sd, int S, int j, int i, float2 (&y)[1 << K]) {
   for (int c = 0; c < R; ++c) y[c] = cur[c];
 }
 
+template <int K, bool DST, typename SP>
+QFT_HD void bwd_group_load(SP sd, int S, int j, int i, float2 (&y)[1 << K]) {
+  constexpr int R = 1 << K;
+  const int G = S >> K;
+  const int base = j * S;
+  float2 cur[R], halo[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) cur[c] = sd[base + c * G + i];
+  const bool has = DST ? (i >= 1) : (i + 1 < G);
+  const int hi = DST ? i - 1 : i + 1;
+#pragma unroll
+  for (int c = 0; c < R; ++c)
+    halo[c] = (c > 0 && has) ? (float2)sd[base + c * G + hi] : make_float2(0.f, 0.f);
+  bwd_group_levels<K, DST>(cur, halo, y);
+}
+
+// bwd_group_load with the sub-segment length G known at compile time (a
+// multiple of the LDS padding block) and the segment starting at cell base:
+// every load is a row access.
+template <int K, int G, bool DST, typename SP>
+QFT_HD void bwd_group_load_s(SP sd, int base, int i, float2 (&y)[1 << K]) {
+  constexpr int R = 1 << K;
+  float2 cur[R], halo[R];
+  const bool has = DST ? (i >= 1) : (i + 1 < G);
+  const auto rc = pad_row(sd, base + i);
+  const auto rh = pad_row(sd, base + (has ? (DST ? i - 1 : i + 1) : i));
+#pragma unroll
+  for (int c = 0; c < R; ++c) cur[c] = rc[c * G];
+#pragma unroll
+  for (int c = 0; c < R; ++c) halo[c] = (c > 0 && has) ? (float2)rh[c * G] : make_float2(0.f, 0.f);
+  bwd_group_levels<K, DST>(cur, halo, y);
+}
+
 // The segment j == 0 of a side head (heap) holds the blocks M = 2G, 4G, ..,
 // S/2 that still need a rounds each (M = G 2^a); the lane-i thread loads the
 // a-level groups of all of them into out[] (2^K - 2 values).
@@ -472,6 +530,29 @@ QFT_HD void bwd_head_store(SP sd, int G, int i, const float2* in) {
 #pragma unroll
     for (int e = 0; e < (1 << A); ++e) sd[M + i * (1 << A) + e] = in[e];
     bwd_head_store<K, A + 1>(sd, G, i, in + (1 << A));
+  }
+}
+
+// bwd_head_load / bwd_head_store with G known at compile time (row accesses;
+// the outputs of one item are a run inside one padding block).
+template <int K, bool DST, int A, int G, typename SP>
+QFT_HD void bwd_head_load_s(SP sd, int i, float2* out) {
+  if constexpr (A < K) {
+    float2 y[1 << A];
+    bwd_group_load_s<A, G, DST>(sd, G << A, i, y);
+#pragma unroll
+    for (int e = 0; e < (1 << A); ++e) out[e] = y[e];
+    bwd_head_load_s<K, DST, A + 1, G>(sd, i, out + (1 << A));
+  }
+}
+
+template <int K, int A, int G, typename SP>
+QFT_HD void bwd_head_store_s(SP sd, int i, const float2* in) {
+  if constexpr (A < K) {
+    const auto r = pad_row(sd, (G << A) + i * (1 << A));
+#pragma unroll
+    for (int e = 0; e < (1 << A); ++e) r.run(e) = in[e];
+    bwd_head_store_s<K, A + 1, G>(sd, i, in + (1 << A));
   }
 }
 
@@ -1031,10 +1112,14 @@ QFT_HD void fwd_group_s(SP sd, int j, int x, const float* __restrict__ sec, bool
   constexpr int NE = 2 << K;
   const int base = j * S;
   float2 e[NE];
+  // rows at x and G-1-x (G a multiple of the padding block)
+  static_assert(G % 8 == 0, "forward group below the padding block");
+  const auto rx = pad_row(sd, base + x);
+  const auto rm = pad_row(sd, base + G - 1 - x);
 #pragma unroll
   for (int c = 0; c < (1 << K); ++c) {
-    e[2 * c] = sd[base + c * G + x];
-    e[2 * c + 1] = sd[base + c * G + G - 1 - x];
+    e[2 * c] = rx[c * G];
+    e[2 * c + 1] = rm[c * G];
   }
 #pragma unroll
   for (int m = K; m >= 1; --m) {
@@ -1064,8 +1149,8 @@ QFT_HD void fwd_group_s(SP sd, int j, int x, const float* __restrict__ sec, bool
   }
 #pragma unroll
   for (int c = 0; c < (1 << K); ++c) {
-    sd[base + c * G + x] = e[2 * c];
-    sd[base + c * G + G - 1 - x] = e[2 * c + 1];
+    rx[c * G] = e[2 * c];
+    rm[c * G] = e[2 * c + 1];
   }
 }
 
@@ -1115,9 +1200,13 @@ QFT_HD void bwd_chunk_s(WP W, int tid, Sync sync) {
   constexpr int R = 1 << K;
   constexpr int S = 1 << (LO + K - 1);
   constexpr int lgG = LO - 1;
+  constexpr int G = 1 << lgG;
   constexpr int lgGroups = LGS - K;
   constexpr int total = NS << lgGroups;
   constexpr int NI = (total + NT - 1) / NT;
+  // row accesses: sub-segments span whole padding blocks, and the R <= 8
+  // outputs of an item lie in one block (sides start on a block boundary)
+  static_assert(lgG >= 3 && K <= 3, "backward chunk below the padding block");
   float2 y[NI][R];
 #pragma unroll
   for (int it = 0; it < NI; ++it) {
@@ -1125,15 +1214,15 @@ QFT_HD void bwd_chunk_s(WP W, int tid, Sync sync) {
     if ((total % NT) != 0 && i >= total) break;
     const int s = i >> lgGroups;
     const int g = i & ((1 << lgGroups) - 1);
-    const int j = g >> lgG, ii = g & ((1 << lgG) - 1);
+    const int j = g >> lgG, ii = g & (G - 1);
     auto sd = W + (s << LGS);
     const bool dst = MODE == SIDES_DST || (MODE == SIDES_ALT && (s & 1));
     if (SKIP0 && j == 0) {
-      if (dst) bwd_head_load<K, true, 1>(sd, 1 << lgG, ii, y[it]);
-      else bwd_head_load<K, false, 1>(sd, 1 << lgG, ii, y[it]);
+      if (dst) bwd_head_load_s<K, true, 1, G>(sd, ii, y[it]);
+      else bwd_head_load_s<K, false, 1, G>(sd, ii, y[it]);
     } else {
-      if (dst) bwd_group_load<K, true>(sd, S, j, ii, y[it]);
-      else bwd_group_load<K, false>(sd, S, j, ii, y[it]);
+      if (dst) bwd_group_load_s<K, G, true>(sd, j * S, ii, y[it]);
+      else bwd_group_load_s<K, G, false>(sd, j * S, ii, y[it]);
     }
   }
   sync();
@@ -1143,13 +1232,14 @@ QFT_HD void bwd_chunk_s(WP W, int tid, Sync sync) {
     if ((total % NT) != 0 && i >= total) break;
     const int s = i >> lgGroups;
     const int g = i & ((1 << lgGroups) - 1);
-    const int j = g >> lgG, ii = g & ((1 << lgG) - 1);
+    const int j = g >> lgG, ii = g & (G - 1);
     auto sd = W + (s << LGS);
     if (SKIP0 && j == 0) {
-      bwd_head_store<K, 1>(sd, 1 << lgG, ii, y[it]);
+      bwd_head_store_s<K, 1, G>(sd, ii, y[it]);
     } else {
+      const auto r = pad_row(sd, j * S + ii * R);
 #pragma unroll
-      for (int e = 0; e < R; ++e) sd[j * S + ii * R + e] = y[it][e];
+      for (int e = 0; e < R; ++e) r.run(e) = y[it][e];
     }
   }
   sync();
@@ -1339,12 +1429,29 @@ QFT_HD constexpr ChainPairing chain_pairing(int P, int K) {
 template <int P, int K, bool DST, typename SP>
 QFT_HD void chain_generic(SP sd, int k, float2* v) {
   float2 o[1 << K];
+  if constexpr (P >= 32) {
+    // every index is a multiple C >= P/4 of P/4 (itself a multiple of 8)
+    // plus k or -k: rows at k and P/4 - k (both >= 0)
+    constexpr int A = P / 4;
+    const auto rp = pad_row(sd, k - (DST ? 1 : 0));
+    const auto rm = pad_row(sd, A - k - (DST ? 1 : 0));
 #pragma unroll
-  for (int l = 0; l < K; ++l) {
-    const int Q4 = (P << l) >> 2;
+    for (int l = 0; l < K; ++l) {
+      const int Q4 = (P << l) >> 2;
 #pragma unroll
-    for (int m = 0; m < (1 << l); ++m)
-      o[(1 << l) - 1 + m] = sd[Q4 + chain_c(P, l, m) + chain_sgn(l, m) * k - (DST ? 1 : 0)];
+      for (int m = 0; m < (1 << l); ++m) {
+        const int C = Q4 + chain_c(P, l, m);
+        o[(1 << l) - 1 + m] = chain_sgn(l, m) > 0 ? (float2)rp[C] : (float2)rm[C - A];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+      const int Q4 = (P << l) >> 2;
+#pragma unroll
+      for (int m = 0; m < (1 << l); ++m)
+        o[(1 << l) - 1 + m] = sd[Q4 + chain_c(P, l, m) + chain_sgn(l, m) * k - (DST ? 1 : 0)];
+    }
   }
   v[0] = sd[k];
 #pragma unroll
@@ -1360,8 +1467,21 @@ QFT_HD void chain_generic(SP sd, int k, float2* v) {
 
 template <int P, int K, typename SP>
 QFT_HD void chain_generic_store(SP sd, int k, const float2* v) {
+  if constexpr (P >= 16) {
+    // output indices: multiples of P/2 (itself a multiple of 8) plus k, or
+    // multiples C >= P/2 minus k: rows at k and P/2 - k (both >= 0)
+    constexpr int A = P / 2;
+    const auto rp = pad_row(sd, k);
+    const auto rm = pad_row(sd, A - k);
 #pragma unroll
-  for (int m = 0; m < (1 << K); ++m) sd[chain_c(P, K, m) + chain_sgn(K, m) * k] = v[m];
+    for (int m = 0; m < (1 << K); ++m) {
+      if (chain_sgn(K, m) > 0) rp[chain_c(P, K, m)] = v[m];
+      else rm[chain_c(P, K, m) - A] = v[m];
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < (1 << K); ++m) sd[chain_c(P, K, m) + chain_sgn(K, m) * k] = v[m];
+  }
 }
 
 // Group 0 of one side, levels L .. K-1 of the pass (v holds the list of
@@ -1987,31 +2107,69 @@ QFT_HD void tile_body_s(const IO& io, WP W, int Tact, const float* sec, int tid,
                         WSync wsync) {
   constexpr int n = 1 << LOGN, h = n >> 1;
   constexpr int total = T << (LOGN - 1);
-  constexpr int FI = (total + NT - 1) / NT;
+  constexpr int FI = total / NT;
+  static_assert(total % NT == 0, "fold items per thread");
   const int tot_act = Tact << (LOGN - 1);
+  // Fold: item it of a thread is the pair (m, N - m) of transform t; the
+  // pair goes to heap cell (N >> (l + 2)) + (m >> (l + 1)), l = ctz(m), of
+  // both sides (m = 0: cells 0 and N/2).
   typename IO::Raw raw[FI];
+  if constexpr (h >= NT) {
+    // t = it NT / h, m = tid + (it NT mod h): for tid != 0 the low bits of
+    // m, hence l, are tid's, and the cell is a per-thread base plus a
+    // constant shifted by l
 #pragma unroll
-  for (int it = 0; it < FI; ++it) {
-    const int i = tid + it * NT;
-    if (i < tot_act) io.fetch(i >> (LOGN - 1), i & (h - 1), raw[it]);
-  }
+    for (int it = 0; it < FI; ++it) {
+      const int t = (it * NT) / h;
+      if (t < Tact) io.fetch(t, tid + (it * NT) % h, raw[it]);
+    }
+    const int l = __builtin_ctz(tid | NT);
+    const int cb = (n >> (l + 2)) + (tid >> (l + 1));
 #pragma unroll
-  for (int it = 0; it < FI; ++it) {
-    const int i = tid + it * NT;
-    if (i < tot_act) {
-      const int t = i >> (LOGN - 1);
-      const int m = i & (h - 1);
-      auto w = W + (t << LOGN);
-      float2 lo, hi;
-      io.fold(raw[it], m, lo, hi);
-      if (m == 0) {
-        w[0] = lo;  // c(0)
-        w[h] = hi;  // c(N/2)
-      } else {
-        const int l = __builtin_ctz(m);
-        const int cell = (n >> (l + 2)) + (m >> (l + 1));
-        w[cell] = lo;
-        w[h + cell] = hi;
+    for (int it = 0; it < FI; ++it) {
+      const int t = (it * NT) / h, C = (it * NT) % h;
+      if (t < Tact) {
+        auto w = W + (t << LOGN);
+        float2 lo, hi;
+        io.fold(raw[it], tid + C, lo, hi);
+        if (tid != 0) {
+          const int cell = cb + (C >> (l + 1));
+          w[cell] = lo;
+          w[h + cell] = hi;
+        } else if (C == 0) {
+          w[0] = lo;  // c(0)
+          w[h] = hi;  // c(N/2)
+        } else {
+          const int lc = __builtin_ctz(C);
+          const int cell = (n >> (lc + 2)) + (C >> (lc + 1));
+          w[cell] = lo;
+          w[h + cell] = hi;
+        }
+      }
+    }
+  } else {
+    // every item of a thread has m = tid mod h; t steps by NT / h
+    constexpr int TS = NT / h;
+    const int m = tid & (h - 1);
+    const int t0 = tid >> (LOGN - 1);
+#pragma unroll
+    for (int it = 0; it < FI; ++it)
+      if (t0 + it * TS < Tact) io.fetch(t0 + it * TS, m, raw[it]);
+    int c1 = 0, c2 = h;
+    if (m != 0) {
+      const int l = __builtin_ctz(m);
+      c1 = (n >> (l + 2)) + (m >> (l + 1));
+      c2 = h + c1;
+    }
+    const auto r1 = pad_row(W, (t0 << LOGN) + c1);
+    const auto r2 = pad_row(W, (t0 << LOGN) + c2);
+#pragma unroll
+    for (int it = 0; it < FI; ++it) {
+      if (t0 + it * TS < Tact) {
+        float2 lo, hi;
+        io.fold(raw[it], m, lo, hi);
+        r1[it * TS * n] = lo;
+        r2[it * TS * n] = hi;
       }
     }
   }

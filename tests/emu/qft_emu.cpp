@@ -100,6 +100,30 @@ struct TPtr {
   TPtr operator+(int64_t d) const { return TPtr{base, off + d, tr, size, ps}; }
 };
 
+// Row accesses of the kernels (pad_row in qft_device.hpp) on an emulated
+// buffer: the exact cell, plus a check of the condition under which the
+// GPU's padded row arithmetic is exact (an access that breaks it counts as
+// out of bounds, so the test fails).
+struct TRow {
+  TPtr t;
+  int64_t blk() const { return t.ps ? (int64_t)1 << t.ps : 0; }
+  Ref operator[](int64_t k) const {
+    if (blk() && (k % blk()) != 0) t.tr->oob++;
+    return t[k];
+  }
+  Ref run(int64_t e) const {
+    if (blk()) {
+      const int64_t b = blk(), m = ((t.off % b) + b) % b;
+      if (e < 0 || m + e >= b) t.tr->oob++;
+    }
+    return t[e];
+  }
+};
+inline TRow pad_row(const TPtr& sd, int a) {
+  if (sd.ps && sd.off + a < 0) sd.tr->oob++;  // rows are anchored inside the buffer
+  return TRow{sd + a};
+}
+
 constexpr int kEmuPad = 3;  // same LDS padding as the GPU kernels
 
 // Runs fn(tid, sync) on nthr threads sharing one barrier whose completion
@@ -428,14 +452,19 @@ template <int DT, bool SWAP, int MC_LOG2>
 int twopass_mc(const void* x, void* X, int64_t batch) {
   using E = typename qftk::Store<DT>::T;
   constexpr int MC = 1 << MC_LOG2;
-  // threads per workgroup: the GPU's 512 for 2^12-cell segments, else <= 32
-  constexpr int NT = MC_LOG2 >= 12 ? 512 : (MC < 32 ? MC : 32);
+  // threads per workgroup: the GPU's (16 cells per thread: 512 for 2^12-cell
+  // segments, 1024 for 2^13), else <= 32
+  constexpr int NT = MC_LOG2 >= 12 ? (2 * MC) / 16 : (MC < 32 ? MC : 32);
   constexpr int logn = MC_LOG2 + 3;
   const int64_t cells = batch << logn;
   std::vector<float> sec = secants(logn);
   std::vector<float2> heap(cells, make_float2(0.f, 0.f));
   int64_t races = 0;
-  // pass A: both sides of one segment per workgroup, 4 workgroups per transform
+  // pass A: both sides of one segment per workgroup, 4 workgroups per
+  // transform, tracked writes of the heap buffer (no two workgroups may
+  // write one cell)
+  Tracker atr(NT);
+  TPtr A{heap.data(), 0, &atr, cells};
   for (int64_t t = 0; t < batch; ++t) {
     for (int j = 0; j < 4; ++j) {
       const int64_t lc = 2 * MC + 1;
@@ -443,14 +472,18 @@ int twopass_mc(const void* x, void* X, int64_t batch) {
       Tracker ltr(NT);
       TPtr L{lds.data(), 0, &ltr, lc, kEmuPad};
       const E* xt = (const E*)x + (t << logn);
-      float2* wt = heap.data() + (t << logn);
       run_workgroup(NT, ltr, [&](int tid, auto sync) {
-        qftk::tp_pass_a2<DT, SWAP, MC_LOG2, NT, 64>(xt, wt, L, j, sec.data(), tid, sync, sync);
+        tl_actor = (t * 4 + j) * NT + tid;  // unique over all workgroups
+        qftk::tp_pass_a2<DT, SWAP, MC_LOG2, NT, 64>(xt, A + (t << logn), L, j, sec.data(), tid,
+                                                    sync, sync);
       });
       if (ltr.oob) return -102;
       races += ltr.races;
     }
   }
+  atr.end_phase();
+  if (atr.oob) return -103;
+  races += atr.races;
   // pass B: N/8 items per transform, tracked reads of the heap buffer
   Tracker gtr(1);
   TPtr G{heap.data(), 0, &gtr, cells};

@@ -174,7 +174,8 @@ def test_two_pass_small(emu, mc_log2, swap):
     both sides of a segment with the fold and the top round from x, runs the
     segment's remaining rounds (and, for the head, the DCT-0/DST-0 chain up to
     P = 2 * segment) in LDS; pass B streams the top backward round, chain
-    levels N/2 and N and the combine."""
+    levels N/2 and N and the combine.  The race tracker checks that no two
+    workgroups of pass A write one heap cell."""
     logn = mc_log2 + 3
     x = workloads.normal(500 + mc_log2, (3, 1 << logn))
     races, out = run_tp(emu, x, mc_log2, swap=swap)
@@ -184,12 +185,13 @@ def test_two_pass_small(emu, mc_log2, swap):
 
 @pytest.mark.slow
 def test_two_pass_library_size(emu):
-    """N = 2^15 with the library's 2^12-cell segments (512 threads, as
-    launched)."""
-    x = workloads.normal(15, (1, 1 << 15))
-    races, out = run_tp(emu, x, 12)
-    assert races == 0
-    assert D.relative_l2(out, _ref(x)).max() <= _tol(15)
+    """N = 2^15 and 2^16 with the library's 2^12- and 2^13-cell segments
+    (512 and 1024 threads, as launched)."""
+    for mc in (12, 13):
+        x = workloads.normal(15, (1, 8 << mc))
+        races, out = run_tp(emu, x, mc)
+        assert races == 0
+        assert D.relative_l2(out, _ref(x)).max() <= _tol(mc + 3)
 
 
 @pytest.mark.parametrize("logn", range(1, 15))
