@@ -1031,70 +1031,6 @@ QFT_HD void mp_bwd_group_item(RP Win, WP Wout, int logn, int s, int64_t i) {
   }
 }
 
-// Segment pass, one workgroup: block r of transform heap wt (length 2^logn)
-// with segments of MC = 2^MC_LOG2 cells and LDS buffer L of 2 MC cells.
-// r == 0: the core (both side heads [0, MC), a virtual transform of 2 MC
-// cells; chain to P = 2 MC); r >= 1: segment j >= 1 of the DCT side, then of
-// the DST side (rounds S = MC .. 2 and back; every sub-segment is a block).
-template <int MC_LOG2, int CPT, class Sync, class WSync, typename GP, typename LP>
-QFT_HD void mp_segment_body(GP wt, LP L, int logn, int r, const float* sec, int tid, int nthr,
-                            int wave_size, Sync sync, WSync wsync) {
-  constexpr int MC = 1 << MC_LOG2;
-  const int h = 1 << (logn - 1);
-  const int segs = h >> MC_LOG2;
-  // CPT = cells per thread for the 2*MC-cell core; the copies below issue all
-  // of a thread's global loads before the LDS stores
-  if (r == 0) {
-    float2 v[CPT];
-#pragma unroll
-    for (int it = 0; it < CPT; ++it) {
-      const int i = tid + it * nthr;
-      if (i < 2 * MC) v[it] = wt[(i >> MC_LOG2) * h + (i & (MC - 1))];
-    }
-#pragma unroll
-    for (int it = 0; it < CPT; ++it) {
-      const int i = tid + it * nthr;
-      if (i < 2 * MC) L[i] = v[it];
-    }
-    sync();
-    mid_sweeps2<CPT>(L, MC_LOG2 + 1, 1, sec, tid, nthr, wave_size, sync, wsync);
-#pragma unroll
-    for (int it = 0; it < CPT; ++it) {
-      const int i = tid + it * nthr;
-      if (i < 2 * MC) wt[(i >> MC_LOG2) * h + (i & (MC - 1))] = (float2)L[i];
-    }
-  } else {
-    const int side = (r - 1) / (segs - 1);
-    const int j = 1 + (r - 1) - side * (segs - 1);
-    auto seg = wt + (side * h + j * MC);
-    constexpr int NI = (CPT + 1) / 2;
-    float2 v[NI];
-#pragma unroll
-    for (int it = 0; it < NI; ++it) {
-      const int i = tid + it * nthr;
-      if (i < MC) v[it] = seg[i];
-    }
-#pragma unroll
-    for (int it = 0; it < NI; ++it) {
-      const int i = tid + it * nthr;
-      if (i < MC) L[i] = v[it];
-    }
-    sync();
-    const int mode = side ? SIDES_DST : SIDES_DCT;
-    sweeps2<CPT>(L, MC_LOG2, 1, mode, MC_LOG2, false, sec, tid, nthr, sync);
-#pragma unroll
-    for (int it = 0; it < NI; ++it) {
-      const int i = tid + it * nthr;
-      if (i < MC) seg[i] = (float2)L[i];
-    }
-  }
-}
-
-// Workgroups per transform of the segment pass.
-QFT_HD int mp_segment_blocks(int logn, int mc_log2) {
-  const int segs = 1 << (logn - 1 - mc_log2);
-  return 1 + 2 * (segs - 1);
-}
 
 
 // ===========================================================================
@@ -2387,14 +2323,15 @@ QFT_HD void tp_gather23(const typename Store<DT>::T* xt, int q, const float* __r
   vs3 = cscale(cadd(d0, d1), hs);
 }
 
-// Segment j of pass A once its cells are in LDS (DCT at L[0, MC), DST at
-// L[MC, 2MC), the top cell at L[2MC]): the remaining rounds, for the head the
-// DCT-0/DST-0 chain up to P = 2 MC, and the copy to the heap buffer.  Starts
-// with a barrier (the caller's LDS stores) and leaves LDS being read.
+// Segment j of a transform heap wt with sides of h cells once both sides'
+// segment j is in LDS (DCT at L[0, MC), DST at L[MC, 2MC), for j = 0 the top
+// cell at L[2MC]): the remaining rounds, for the head the DCT-0/DST-0 chain
+// up to P = 2 MC, and the copy to the heap buffer.  Starts with a barrier
+// (the caller's LDS stores) and leaves LDS being read.
 template <int MC_LOG2, int NT, int WAVE, class Sync, class WSync, typename GP, typename LP>
-QFT_HD void tp_segment(GP wt, LP L, int j, const float* sec, int tid, Sync sync, WSync wsync) {
+QFT_HD void tp_segment(GP wt, LP L, int j, int h, const float* sec, int tid, Sync sync,
+                       WSync wsync) {
   constexpr int MC = 1 << MC_LOG2;
-  constexpr int h = 4 * MC;
   constexpr int NI = MC / NT;
   sync();
   if (j == 0) {
@@ -2450,7 +2387,32 @@ QFT_HD void tp_pass_a2(const typename Store<DT>::T* xt, GP wt, LP L, int j, cons
     L[MC + q] = vs[it];
   }
   if (j == 0 && tid == 0) L[2 * MC] = topv;
-  tp_segment<MC_LOG2, NT, WAVE>(wt, L, j, sec, tid, sync, wsync);
+  tp_segment<MC_LOG2, NT, WAVE>(wt, L, j, h, sec, tid, sync, wsync);
+}
+
+// Segment pass of the multi-pass path: workgroup j of transform heap wt
+// (sides of h cells) loads segment j of both sides (j = 0: the side heads
+// and the top cell) and runs tp_segment on them.
+template <int MC_LOG2, int NT, int WAVE, class Sync, class WSync, typename GP, typename LP>
+QFT_HD void mp_segment_pair(GP wt, LP L, int h, int j, const float* sec, int tid, Sync sync,
+                            WSync wsync) {
+  constexpr int MC = 1 << MC_LOG2;
+  constexpr int NI = MC / NT;
+  float2 vc[NI], vs[NI];
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int q = tid + it * NT;
+    vc[it] = wt[j * MC + q];
+    vs[it] = wt[h + j * MC + q];
+  }
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int q = tid + it * NT;
+    L[q] = vc[it];
+    L[MC + q] = vs[it];
+  }
+  if (j == 0 && tid == 0) L[2 * MC] = (float2)wt[h];  // top cell (DST cell 0)
+  tp_segment<MC_LOG2, NT, WAVE>(wt, L, j, h, sec, tid, sync, wsync);
 }
 
 }  // namespace qftk

@@ -6,9 +6,10 @@
 //   fold        x -> heap (through the plan's IO accessor)
 //   fwd         up to 4 forward rounds of the large blocks per pass, in
 //               registers, in place
-//   segment     one workgroup per 2^12-cell segment: its remaining forward
-//               and its backward rounds in LDS; workgroup 0 of a transform
-//               also runs both side heads and the chain to P = 2^13
+//   segment     one workgroup per 2^12-cell segment index: the segment of
+//               both sides, its remaining forward and its backward rounds in
+//               LDS; workgroup 0 of a transform takes both side heads and
+//               also runs the chain to P = 2^13
 //   bwd         up to 5 backward rounds per pass, heap -> other buffer
 //   chain       up to 5 chain levels per pass, E values and outputs in the
 //               chain buffer, DCT-II / DST-II blocks read from the heap
@@ -63,21 +64,25 @@ __global__ __launch_bounds__(MP_BLOCK) void mp_combine_kernel(IO io, const float
 
 #undef QFT_GRID_STRIDE
 
+// Segment pass: workgroup (t, j) takes segment j of both sides of transform
+// t (j = 0: the side heads and the top cell), 16 cells per thread.
 template <int MC_LOG2, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void mp_segment_kernel(float2* W, int logn,
                                                            const float* sec) {
   constexpr int MC = 1 << MC_LOG2;
-  constexpr int CPT = (2 * MC) / BLOCK;
-  __shared__ float2 Ll[padded_cells<kPad>(2 * MC)];
+  static_assert(2 * MC == 16 * BLOCK, "16 cells per thread");
+  __shared__ float2 Ll[padded_cells<kPad>(2 * MC + 1)];
   const PadPtr<kPad> L{Ll, 0};
-  const int per_t = mp_segment_blocks(logn, MC_LOG2);
-  const int64_t t = blockIdx.x / per_t;
-  const int r = (int)(blockIdx.x - t * per_t);
-  mp_segment_body<MC_LOG2, CPT>(W + (t << logn), L, logn, r, sec, (int)threadIdx.x, BLOCK, kWave,
-                                DevSync{}, DevWaveSync{});
+  const int lgsegs = logn - 1 - MC_LOG2;
+  const int64_t t = (int64_t)blockIdx.x >> lgsegs;
+  const int j = (int)(blockIdx.x & ((1u << lgsegs) - 1));
+  mp_segment_pair<MC_LOG2, BLOCK, kWave>(W + (t << logn), L, 1 << (logn - 1), j, sec,
+                                         (int)threadIdx.x, DevSync{}, DevWaveSync{});
 }
 
 namespace {
+
+constexpr int kMpSegThreads = (2 << kMpSegLog2) / 16;
 
 // Most forward rounds, backward rounds and chain levels per global pass
 // (QFT_MP_LEVELS=f,b,c overrides the defaults at build time).
@@ -128,9 +133,9 @@ struct GpuMultipass {
     }
   }
   void segment() {
-    const int64_t blocks = batch * mp_segment_blocks(logn, kMpSegLog2);
-    hipLaunchKernelGGL((mp_segment_kernel<kMpSegLog2, 256>), dim3((unsigned)blocks), dim3(256),
-                       0, st, cur, logn, sec);
+    const int64_t blocks = batch << (logn - 1 - kMpSegLog2);
+    hipLaunchKernelGGL((mp_segment_kernel<kMpSegLog2, kMpSegThreads>), dim3((unsigned)blocks),
+                       dim3(kMpSegThreads), 0, st, cur, logn, sec);
   }
   template <int K>
   void bwd_k(int hi) {
@@ -186,7 +191,7 @@ template <class IO>
 hipError_t run_multipass(const IO& io, int log2n, int64_t batch, const float* sec, float2* W0,
                          float2* W1, hipStream_t st) {
   if (log2n < kMpSegLog2 + 3 || log2n > 24 || batch < 1 ||
-      batch * mp_segment_blocks(log2n, kMpSegLog2) > 0x7fffffff)
+      (batch << (log2n - 1 - kMpSegLog2)) > 0x7fffffff)
     return hipErrorInvalidValue;
   GpuMultipass<IO> ex{io, log2n, batch, sec, W0, W1, st};
   multipass_schedule(ex, log2n, kMpSegLog2, kLevels);

@@ -308,18 +308,20 @@ struct EmuMultipass {
   }
   template <int MC_LOG2>
   void segment_mc() {
-    const int per_t = qftk::mp_segment_blocks(logn, MC_LOG2);
-    for (int64_t b = 0; b < batch * per_t; ++b) {
-      const int64_t t = b / per_t;
-      const int r = (int)(b - t * per_t);
-      const int64_t lc = (int64_t)2 << MC_LOG2;
+    // the GPU's 16 cells per thread for 2^12-cell segments, else <= 32
+    constexpr int MC = 1 << MC_LOG2;
+    constexpr int NT = MC_LOG2 >= 12 ? (2 * MC) / 16 : (MC < 32 ? MC : 32);
+    const int segs = 1 << (logn - 1 - MC_LOG2);
+    for (int64_t b = 0; b < batch * segs; ++b) {
+      const int64_t t = b / segs;
+      const int j = (int)(b - t * segs);
+      const int64_t lc = 2 * MC + 1;
       std::vector<float2> lds(lc + (lc >> kEmuPad));
-      Tracker ltr(nthr);
+      Tracker ltr(NT);
       TPtr L{lds.data(), 0, &ltr, lc, kEmuPad};
       float2* wt = cur + (t << logn);
-      run_workgroup(nthr, ltr, [&](int tid, auto sync) {
-        qftk::mp_segment_body<MC_LOG2, kEmuCpt>(wt, L, logn, r, sec, tid, nthr, kEmuWave, sync,
-                                                sync);
+      run_workgroup(NT, ltr, [&](int tid, auto sync) {
+        qftk::mp_segment_pair<MC_LOG2, NT, 64>(wt, L, 1 << (logn - 1), j, sec, tid, sync, sync);
       });
       races += ltr.races;
       if (ltr.oob) races = -1000000;
