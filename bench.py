@@ -122,6 +122,23 @@ def extra_workloads(dev, stream):
     best = up.schedules[up.schedule]
     ums = time_ms(lambda: qft.qft_exec_fwd(up.handle, ut.data_ptr(), uo.data_ptr(), sp),
                   stream, 20, 3)
+    eager = uo.clone()
+    # the autotuned exec captured in a HIP graph (torch.cuda.CUDAGraph), replayed
+    gs = torch.cuda.Stream(dev)
+    gs.wait_stream(stream)
+    with torch.cuda.stream(gs):
+        qft.qft_exec_fwd(up.handle, ut.data_ptr(), uo.data_ptr(), gs.cuda_stream)
+    stream.wait_stream(gs)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        qft.qft_exec_fwd(up.handle, ut.data_ptr(), uo.data_ptr(),
+                         torch.cuda.current_stream().cuda_stream)
+    uo.zero_()
+    torch.cuda.synchronize()
+    gms = time_ms(graph.replay, stream, 20, 3)
+    graph_equal = bool(torch.equal(uo, eager))
+    del graph, eager
     h16 = torch.from_numpy(np.stack([vals.real, vals.imag], -1).astype(np.float16)).to(dev)
     u16 = h16.view(torch.complex32).reshape(-1)
     o16 = torch.empty_like(u16)
@@ -136,6 +153,7 @@ def extra_workloads(dev, stream):
         "autotuned_schedule": best,
         "schedule_ms": {k: round(v, 5) for k, v in tuned.items()},
         "fp32_ms": round(ums, 5), "fp32_GBps": round(16 * tot / (ums * 1e-3) / 1e9, 1),
+        "hip_graph_replay_ms": round(gms, 5), "hip_graph_replay_bit_equal": graph_equal,
         "fp16_storage_ms": round(ums16, 5),
         "fp16_storage_GBps": round(8 * tot / (ums16 * 1e-3) / 1e9, 1),
         "GFLOPs_5nlogn_fp32": round(up.info["flops_5nlogn"] / (ums * 1e-3) / 1e9, 1),

@@ -348,13 +348,13 @@ struct PadRow {
   QFT_HD float2& run(int e) const { return p[e]; }
 };
 
-// Callers index rows with multiples of 8 cells (the padding block may not be
-// larger) and anchor them at cells >= 0 of the buffer.
-constexpr int kMaxRowPad = 3;
+// Callers index rows with multiples of kRowCells cells (the padding block
+// must divide it) and anchor them at cells >= 0 of the buffer.
+constexpr int kRowCells = 16;
 
 template <int PS>
 QFT_HD PadRow<PS> pad_row(const PadPtr<PS>& sd, int a) {
-  static_assert(PS >= 16 || PS <= kMaxRowPad, "row offsets are multiples of 8 cells");
+  static_assert(PS >= 16 || (1 << PS) <= kRowCells, "row offsets are whole padding blocks");
   const int c = sd.off + a;
   return PadRow<PS>{sd.base + (PS >= 16 ? c : c + (c >> (PS & 15)))};
 }
@@ -492,20 +492,30 @@ QFT_HD void bwd_group_load(SP sd, int S, int j, int i, float2 (&y)[1 << K]) {
   bwd_group_levels<K, DST>(cur, halo, y);
 }
 
-// bwd_group_load with the sub-segment length G known at compile time (a
-// multiple of the LDS padding block) and the segment starting at cell base:
-// every load is a row access.
+// bwd_group_load with the sub-segment length G known at compile time and the
+// segment starting at cell base: row accesses when G is a multiple of
+// kRowCells.
 template <int K, int G, bool DST, typename SP>
 QFT_HD void bwd_group_load_s(SP sd, int base, int i, float2 (&y)[1 << K]) {
   constexpr int R = 1 << K;
   float2 cur[R], halo[R];
   const bool has = DST ? (i >= 1) : (i + 1 < G);
-  const auto rc = pad_row(sd, base + i);
-  const auto rh = pad_row(sd, base + (has ? (DST ? i - 1 : i + 1) : i));
+  const int hi = has ? (DST ? i - 1 : i + 1) : i;
+  if constexpr (G % kRowCells == 0) {
+    const auto rc = pad_row(sd, base + i);
+    const auto rh = pad_row(sd, base + hi);
 #pragma unroll
-  for (int c = 0; c < R; ++c) cur[c] = rc[c * G];
+    for (int c = 0; c < R; ++c) cur[c] = rc[c * G];
 #pragma unroll
-  for (int c = 0; c < R; ++c) halo[c] = (c > 0 && has) ? (float2)rh[c * G] : make_float2(0.f, 0.f);
+    for (int c = 0; c < R; ++c)
+      halo[c] = (c > 0 && has) ? (float2)rh[c * G] : make_float2(0.f, 0.f);
+  } else {
+#pragma unroll
+    for (int c = 0; c < R; ++c) cur[c] = sd[base + c * G + i];
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+      halo[c] = (c > 0 && has) ? (float2)sd[base + c * G + hi] : make_float2(0.f, 0.f);
+  }
   bwd_group_levels<K, DST>(cur, halo, y);
 }
 
@@ -1048,14 +1058,19 @@ QFT_HD void fwd_group_s(SP sd, int j, int x, const float* __restrict__ sec, bool
   constexpr int NE = 2 << K;
   const int base = j * S;
   float2 e[NE];
-  // rows at x and G-1-x (G a multiple of the padding block)
-  static_assert(G % 8 == 0, "forward group below the padding block");
+  // rows at x and G-1-x when G is a multiple of kRowCells
+  constexpr bool ROWS = G % kRowCells == 0;
   const auto rx = pad_row(sd, base + x);
   const auto rm = pad_row(sd, base + G - 1 - x);
 #pragma unroll
   for (int c = 0; c < (1 << K); ++c) {
-    e[2 * c] = rx[c * G];
-    e[2 * c + 1] = rm[c * G];
+    if constexpr (ROWS) {
+      e[2 * c] = rx[c * G];
+      e[2 * c + 1] = rm[c * G];
+    } else {
+      e[2 * c] = sd[base + c * G + x];
+      e[2 * c + 1] = sd[base + c * G + G - 1 - x];
+    }
   }
 #pragma unroll
   for (int m = K; m >= 1; --m) {
@@ -1085,8 +1100,13 @@ QFT_HD void fwd_group_s(SP sd, int j, int x, const float* __restrict__ sec, bool
   }
 #pragma unroll
   for (int c = 0; c < (1 << K); ++c) {
-    rx[c * G] = e[2 * c];
-    rm[c * G] = e[2 * c + 1];
+    if constexpr (ROWS) {
+      rx[c * G] = e[2 * c];
+      rm[c * G] = e[2 * c + 1];
+    } else {
+      sd[base + c * G + x] = e[2 * c];
+      sd[base + c * G + G - 1 - x] = e[2 * c + 1];
+    }
   }
 }
 
@@ -1140,9 +1160,9 @@ QFT_HD void bwd_chunk_s(WP W, int tid, Sync sync) {
   constexpr int lgGroups = LGS - K;
   constexpr int total = NS << lgGroups;
   constexpr int NI = (total + NT - 1) / NT;
-  // row accesses: sub-segments span whole padding blocks, and the R <= 8
-  // outputs of an item lie in one block (sides start on a block boundary)
-  static_assert(lgG >= 3 && K <= 3, "backward chunk below the padding block");
+  // the R <= 8 outputs of an item are a run inside one padding block (sides
+  // start on a block boundary)
+  static_assert(K <= 3, "runs of at most 8 cells");
   float2 y[NI][R];
 #pragma unroll
   for (int it = 0; it < NI; ++it) {
@@ -1365,9 +1385,9 @@ QFT_HD constexpr ChainPairing chain_pairing(int P, int K) {
 template <int P, int K, bool DST, typename SP>
 QFT_HD void chain_generic(SP sd, int k, float2* v) {
   float2 o[1 << K];
-  if constexpr (P >= 32) {
-    // every index is a multiple C >= P/4 of P/4 (itself a multiple of 8)
-    // plus k or -k: rows at k and P/4 - k (both >= 0)
+  if constexpr ((P / 4) % kRowCells == 0) {
+    // every index is a multiple C >= P/4 of P/4 plus k or -k: rows at k and
+    // P/4 - k (both >= 0)
     constexpr int A = P / 4;
     const auto rp = pad_row(sd, k - (DST ? 1 : 0));
     const auto rm = pad_row(sd, A - k - (DST ? 1 : 0));
@@ -1403,9 +1423,9 @@ QFT_HD void chain_generic(SP sd, int k, float2* v) {
 
 template <int P, int K, typename SP>
 QFT_HD void chain_generic_store(SP sd, int k, const float2* v) {
-  if constexpr (P >= 16) {
-    // output indices: multiples of P/2 (itself a multiple of 8) plus k, or
-    // multiples C >= P/2 minus k: rows at k and P/2 - k (both >= 0)
+  if constexpr ((P / 2) % kRowCells == 0) {
+    // output indices: multiples of P/2 plus k, or multiples C >= P/2 minus k:
+    // rows at k and P/2 - k (both >= 0)
     constexpr int A = P / 2;
     const auto rp = pad_row(sd, k);
     const auto rm = pad_row(sd, A - k);
@@ -2086,6 +2106,7 @@ QFT_HD void tile_body_s(const IO& io, WP W, int Tact, const float* sec, int tid,
   } else {
     // every item of a thread has m = tid mod h; t steps by NT / h
     constexpr int TS = NT / h;
+    static_assert((TS * n) % kRowCells == 0, "fold rows step by whole row units");
     const int m = tid & (h - 1);
     const int t0 = tid >> (LOGN - 1);
 #pragma unroll

@@ -26,7 +26,11 @@ struct DevWaveSync {
 };
 
 constexpr int kWave = 64;
-constexpr int kPad = 3;  // LDS padding: one spare cell per 2^kPad cells
+// LDS padding: one spare cell per 2^kPad = 16 cells.  Sixteen lanes reading
+// consecutive cells then cover the 32 banks once; lanes owning runs of 16
+// cells (fused tail) start one cell apart, runs of 8 cells (backward outputs)
+// alternate between the two halves of the banks.
+constexpr int kPad = 4;
 
 // Persistent tile kernel with tiles of 2^tl cells (12 <= tl <= 14): 16 cells
 // per thread, and as many resident workgroups per CU as the LDS allows

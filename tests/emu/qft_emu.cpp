@@ -102,13 +102,15 @@ struct TPtr {
 
 // Row accesses of the kernels (pad_row in qft_device.hpp) on an emulated
 // buffer: the exact cell, plus a check of the condition under which the
-// GPU's padded row arithmetic is exact (an access that breaks it counts as
-// out of bounds, so the test fails).
+// GPU's padded row arithmetic is exact for a padding block of up to
+// kRowCells cells (offsets in whole kRowCells, runs inside one 8-cell block,
+// anchors inside the buffer); an access that breaks it counts as out of
+// bounds, so the test fails.
 struct TRow {
   TPtr t;
   int64_t blk() const { return t.ps ? (int64_t)1 << t.ps : 0; }
   Ref operator[](int64_t k) const {
-    if (blk() && (k % blk()) != 0) t.tr->oob++;
+    if (blk() && (k % qftk::kRowCells) != 0) t.tr->oob++;
     return t[k];
   }
   Ref run(int64_t e) const {
@@ -124,7 +126,7 @@ inline TRow pad_row(const TPtr& sd, int a) {
   return TRow{sd + a};
 }
 
-constexpr int kEmuPad = 3;  // same LDS padding as the GPU kernels
+constexpr int kEmuPad = 4;  // same LDS padding as the GPU kernels
 
 // Runs fn(tid, sync) on nthr threads sharing one barrier whose completion
 // closes a tracker phase.
