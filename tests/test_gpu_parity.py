@@ -97,6 +97,26 @@ def test_adjoint_and_round_trip(logn, B):
     assert abs(lhs - rhs) <= tol(logn) * abs(lhs) * 10
 
 
+@pytest.mark.parametrize("logn,B", [(12, 3), (15, 2), (16, 2), (17, 1), (19, 1)])
+def test_fp16_storage_all_paths(logn, B):
+    """FP16 storage with FP32 arithmetic on every path (tile, two-pass,
+    multi-pass), forward and adjoint, against the FP64 oracle on the
+    FP16-rounded input; the output rounding to FP16 bounds the error."""
+    say(f"fp16 storage: N=2^{logn} B={B}")
+    x = workloads.uniform(9000 + logn, (B, 1 << logn)).astype(np.complex64)
+    host = np.stack([x.real, x.imag], -1).astype(np.float16)
+    xin = host[..., 0].astype(np.float64) + 1j * host[..., 1].astype(np.float64)
+    t = torch.from_numpy(host).to(DEV).view(torch.complex32).reshape(B, -1)
+    for adj in (False, True):
+        y = qft.fft_adjoint(t) if adj else qft.fft(t)
+        torch.cuda.synchronize()
+        o = y.view(torch.float16).reshape(B, -1, 2).float().cpu().numpy().astype(np.float64)
+        got = o[..., 0] + 1j * o[..., 1]
+        ref = np.conj(ref_fwd(np.conj(xin))) if adj else ref_fwd(xin)
+        err = D.relative_l2(got, ref).max()
+        assert err <= 1e-3, (adj, err)
+
+
 def test_c2_full_size():
     say("c2: N=2^16 B=256 N(0,1) seed 1 (the benchmark workload), full compare")
     x = workloads.make("c2")
