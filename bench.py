@@ -100,6 +100,21 @@ def extra_workloads(dev, stream):
 
     step = time_ms(train_step, stream, 10, 2)
     grad = train_step().cpu().numpy().astype(np.complex128)
+    # forward then adjoint, both execs captured in one HIP graph and replayed
+    gs = torch.cuda.Stream(dev)
+    gs.wait_stream(stream)
+    with torch.cuda.stream(gs):
+        qft.qft_exec_fwd(plan.handle, xt.data_ptr(), y.data_ptr(), gs.cuda_stream)
+        qft.qft_exec_bwd(plan.handle, y.data_ptr(), g.data_ptr(), gs.cuda_stream)
+    stream.wait_stream(gs)
+    torch.cuda.synchronize()
+    fb_graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(fb_graph):
+        cs = torch.cuda.current_stream().cuda_stream
+        qft.qft_exec_fwd(plan.handle, xt.data_ptr(), y.data_ptr(), cs)
+        qft.qft_exec_bwd(plan.handle, y.data_ptr(), g.data_ptr(), cs)
+    fb_graph_ms = time_ms(fb_graph.replay, stream, 20, 3)
+    del fb_graph
     Xr = OB.cdft(x.astype(np.complex128))
     gref = 2 * np.conj(OB.cdft(np.conj(w * Xr)))
     bytes_dir = 2 * xt.numel() * 8
@@ -108,6 +123,7 @@ def extra_workloads(dev, stream):
         "fwd_ms": round(fwd, 5), "bwd_ms": round(bwd, 5), "fwd_plus_bwd_ms": round(fwd + bwd, 5),
         "fwd_GBps": round(bytes_dir / (fwd * 1e-3) / 1e9, 1),
         "bwd_GBps": round(bytes_dir / (bwd * 1e-3) / 1e9, 1),
+        "fwd_plus_bwd_graph_replay_ms": round(fb_graph_ms, 5),
         "autograd_step_ms": round(step, 5),
         "grad_rel_l2_max": float(f"{D.relative_l2(grad, gref).max():.3e}"),
     }
