@@ -104,58 +104,6 @@ template <bool SWAP> QFT_HD float2 sw(float2 v) {
 }
 
 // ---------------------------------------------------------------------------
-// Fold: x (T transforms of length n, global, element type DT) -> W (heap
-// layout).  rdft fold of Sec. 4.2 and the cell map of the even/odd chain.
-// ---------------------------------------------------------------------------
-template <int DT, bool SWAP, typename WP>
-QFT_HD void fold_to_heap(const typename Store<DT>::T* x, WP W, int logn, int T,
-                          int tid, int nthr) {
-  const int n = 1 << logn, h = n >> 1;
-  const int total = T << (logn - 1);
-  for (int i = tid; i < total; i += nthr) {
-    const int t = i >> (logn - 1);
-    const int m = i & (h - 1);
-    const typename Store<DT>::T* xt = x + ((int64_t)t << logn);
-    auto w = W + (t << logn);
-    if (m == 0) {
-      w[0] = sw<SWAP>(Store<DT>::ld(xt, 0));
-      w[h] = sw<SWAP>(Store<DT>::ld(xt, h));
-    } else {
-      const float2 a = sw<SWAP>(Store<DT>::ld(xt, m));
-      const float2 b = sw<SWAP>(Store<DT>::ld(xt, n - m));
-      const int l = __builtin_ctz(m);
-      const int cell = (n >> (l + 2)) + (m >> (l + 1));
-      w[cell] = cadd(a, b);
-      w[h + cell] = csub(a, b);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Combine: heap layout W -> X (global), cdft combine of Sec. 4.1.
-// ---------------------------------------------------------------------------
-template <int DT, bool SWAP, typename WP>
-QFT_HD void combine_from_heap(WP W, typename Store<DT>::T* X, int logn, int T,
-                               int tid, int nthr) {
-  const int n = 1 << logn, h = n >> 1;
-  const int total = T << (logn - 1);
-  for (int i = tid; i < total; i += nthr) {
-    const int t = i >> (logn - 1);
-    const int k = i & (h - 1);
-    typename Store<DT>::T* Xt = X + ((int64_t)t << logn);
-    auto w = W + (t << logn);
-    if (k == 0) {
-      Store<DT>::st(Xt, 0, sw<SWAP>(w[0]));
-      Store<DT>::st(Xt, h, sw<SWAP>(w[h]));
-    } else {
-      const float2 C = w[k], S = w[h + k];
-      Store<DT>::st(Xt, k, sw<SWAP>(make_float2(C.x + S.y, C.y - S.x)));
-      Store<DT>::st(Xt, n - k, sw<SWAP>(make_float2(C.x - S.y, C.y + S.x)));
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Forward rounds on one register group.  K consecutive rounds S, S/2, ..,
 // S/2^(K-1) on segment j of one side.  With G = S >> K >= 2, the group of
 // lane-offset x < G/2 is the closed cell set
@@ -207,59 +155,6 @@ QFT_HD void fwd_group(SP sd, int S, int j, int x, const float* __restrict__ sec,
   for (int c = 0; c < (1 << K); ++c) {
     sd[base + c * G + x] = e[2 * c];
     sd[base + c * G + G - 1 - x] = e[2 * c + 1];
-  }
-}
-
-// G == 1 variant: K rounds 2^K, .., 2 on the whole segment j (S = 2^K).
-template <int K, bool DST, typename SP>
-QFT_HD void fwd_group_tail(SP sd, int j, const float* __restrict__ sec, bool skip0) {
-  constexpr int S = 1 << K;
-  const int base = j * S;
-  float2 e[S];
-#pragma unroll
-  for (int c = 0; c < S; ++c) e[c] = sd[base + c];
-#pragma unroll
-  for (int m = K; m >= 1; --m) {
-    const int span = 1 << m, half = span >> 1;
-    float2 o[S];
-#pragma unroll
-    for (int i = 0; i < S; ++i) o[i] = e[i];
-#pragma unroll
-    for (int c0 = 0; c0 < S; c0 += span) {
-      if (skip0 && j == 0 && c0 == 0) continue;
-#pragma unroll
-      for (int cc = 0; cc < half; ++cc) {
-        const float2 a = e[c0 + cc], b = e[c0 + span - 1 - cc];
-        const float hsec = sec[half + cc];
-        const float2 s = cadd(a, b), d = csub(a, b);
-        o[c0 + cc] = DST ? d : s;
-        o[c0 + half + cc] = cscale(DST ? s : d, hsec);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < S; ++i) e[i] = o[i];
-  }
-#pragma unroll
-  for (int c = 0; c < S; ++c) sd[base + c] = e[c];
-}
-
-// ---------------------------------------------------------------------------
-// Backward round at segment size S on one item: output cells 2i, 2i+1 of
-// segment j of one side.  Reads A(i), T(i) and the neighbour T(i+1) (DCT)
-// or T(i-1) (DST).  Out of place: the caller stores after a barrier.
-// ---------------------------------------------------------------------------
-template <bool DST, typename SP>
-QFT_HD void bwd_item(SP sd, int S, int j, int i, float2& y0, float2& y1) {
-  const int hS = S >> 1;
-  const int base = j * S;
-  const float2 A = sd[base + i];
-  const float2 T0 = sd[base + hS + i];
-  if (!DST) {
-    y0 = A;
-    y1 = (i + 1 < hS) ? cadd(T0, sd[base + hS + i + 1]) : T0;
-  } else {
-    y1 = A;
-    y0 = (i >= 1) ? cadd(sd[base + hS + i - 1], T0) : T0;
   }
 }
 
@@ -567,115 +462,11 @@ QFT_HD void bwd_head_store_s(SP sd, int i, const float2* in) {
 }
 
 // ===========================================================================
-// Sweeps over a workgroup's buffer.  A "side" is one half of a transform's
-// heap (DCT or DST); transforms alternate DCT/DST sides, an isolated segment
-// of a larger transform is a single side of fixed flavour.  Side s lives at
-// W + s * 2^lgside.  `sync` is the workgroup barrier.
+// Sides.  A "side" is one half of a transform's heap (DCT or DST); the sides
+// of a tile alternate DCT/DST, an isolated segment of a larger transform is
+// a single side of fixed flavour.
 // ===========================================================================
 enum SideMode { SIDES_ALT = 0, SIDES_DCT = 1, SIDES_DST = 2 };
-
-QFT_HD bool side_is_dst(int mode, int s) {
-  return mode == SIDES_ALT ? (s & 1) != 0 : mode == SIDES_DST;
-}
-
-// K forward rounds S = 2^hi .. 2^(hi-K+1).  TAIL: the rounds end at S = 2
-// (G = 1, one group per segment); otherwise G = 2^(hi-K) >= 2.
-template <int K, bool TAIL, typename WP>
-QFT_HD void fwd_chunk(WP W, int lgside, int nsides, int mode, int hi, bool skip0,
-                      const float* sec, int tid, int nthr) {
-  const int lgGroups = TAIL ? (lgside - K) : (lgside - K - 1);  // groups per side
-  const int total = nsides << lgGroups;
-  for (int i = tid; i < total; i += nthr) {
-    const int s = i >> lgGroups;
-    const int g = i & ((1 << lgGroups) - 1);
-    auto sd = W + (s << lgside);
-    const bool dst = side_is_dst(mode, s);
-    if (TAIL) {
-      if (dst) fwd_group_tail<K, true>(sd, g, sec, skip0);
-      else fwd_group_tail<K, false>(sd, g, sec, skip0);
-    } else {
-      const int lgHalfG = hi - K - 1;
-      const int j = g >> lgHalfG;
-      const int x = g & ((1 << lgHalfG) - 1);
-      if (dst) fwd_group<K, true>(sd, 1 << hi, j, x, sec, skip0);
-      else fwd_group<K, false>(sd, 1 << hi, j, x, sec, skip0);
-    }
-  }
-}
-
-// Forward rounds S = 2^top .. 2^bottom in chunks of <= 3 rounds aligned from
-// the bottom; the chunk that ends at S = 2 uses the whole-segment form.
-template <class Sync, typename WP>
-QFT_HD void forward_sweep(WP W, int lgside, int nsides, int mode, int top, int bottom,
-                          bool skip0, const float* sec, int tid, int nthr, Sync sync) {
-  constexpr int KF = 3;
-  if (top < bottom) return;
-  const int R = top - bottom + 1;
-  const int nchunks = (R + KF - 1) / KF;
-  for (int c = nchunks - 1; c >= 0; --c) {
-    const int lo = bottom + c * KF;
-    const int hi = (top < lo + KF - 1) ? top : lo + KF - 1;
-    const int K = hi - lo + 1;
-    const bool tail = (lo == 1);
-    if (K == 3) {
-      if (tail) fwd_chunk<3, true>(W, lgside, nsides, mode, hi, skip0, sec, tid, nthr);
-      else fwd_chunk<3, false>(W, lgside, nsides, mode, hi, skip0, sec, tid, nthr);
-    } else if (K == 2) {
-      if (tail) fwd_chunk<2, true>(W, lgside, nsides, mode, hi, skip0, sec, tid, nthr);
-      else fwd_chunk<2, false>(W, lgside, nsides, mode, hi, skip0, sec, tid, nthr);
-    } else {
-      if (tail) fwd_chunk<1, true>(W, lgside, nsides, mode, hi, skip0, sec, tid, nthr);
-      else fwd_chunk<1, false>(W, lgside, nsides, mode, hi, skip0, sec, tid, nthr);
-    }
-    sync();
-  }
-}
-
-// Backward rounds S = 2^bottom .. 2^top, one round per pass: every thread
-// loads its items into registers, the workgroup synchronises, then stores.
-// Requires MAXI >= ceil(nsides * 2^(lgside-1) / nthr).
-template <int MAXI, class Sync, typename WP>
-QFT_HD void backward_sweep(WP W, int lgside, int nsides, int mode, int bottom, int top,
-                           bool skip0, int tid, int nthr, Sync sync) {
-  const int lgItems = lgside - 1;  // items (output cell pairs) per side
-  const int total = nsides << lgItems;
-  for (int s = bottom; s <= top; ++s) {
-    const int S = 1 << s;
-    float2 y0[MAXI], y1[MAXI];
-#pragma unroll
-    for (int it = 0; it < MAXI; ++it) {
-      const int i = tid + it * nthr;
-      if (i < total) {
-        const int si = i >> lgItems;
-        const int item = i & ((1 << lgItems) - 1);
-        const int j = item >> (s - 1);
-        const int ii = item & ((S >> 1) - 1);
-        if (!(skip0 && j == 0)) {
-          auto sd = W + (si << lgside);
-          if (side_is_dst(mode, si)) bwd_item<true>(sd, S, j, ii, y0[it], y1[it]);
-          else bwd_item<false>(sd, S, j, ii, y0[it], y1[it]);
-        }
-      }
-    }
-    sync();
-#pragma unroll
-    for (int it = 0; it < MAXI; ++it) {
-      const int i = tid + it * nthr;
-      if (i < total) {
-        const int si = i >> lgItems;
-        const int item = i & ((1 << lgItems) - 1);
-        const int j = item >> (s - 1);
-        const int ii = item & ((S >> 1) - 1);
-        if (!(skip0 && j == 0)) {
-          auto sd = W + (si << lgside);
-          sd[j * S + 2 * ii] = y0[it];
-          sd[j * S + 2 * ii + 1] = y1[it];
-        }
-      }
-    }
-    sync();
-  }
-}
 
 // DCT-0 / DST-0 chain level P = 2^p (p >= 1) for transform heap dc (length
 // 2^logn): group g of the level (see chain_*_group).  Groups per transform:
@@ -697,269 +488,6 @@ QFT_HD void chain_item(WP dc, int logn, int p, int g) {
   const int ngd = (P == 4) ? 1 : 1 + (P >> 3);
   if (g < ngd) chain_dct_group(dc, dc + h, P, g);
   else chain_dst_group(dc + h, P, g - ngd);
-}
-
-template <class Sync, typename WP>
-QFT_HD void chain_sweep(WP W, int logn, int T, int lo, int hi, int tid, int nthr, Sync sync) {
-  for (int p = lo; p <= hi; ++p) {
-    const int per_t = chain_groups(p);
-    const int total = T * per_t;
-    for (int i = tid; i < total; i += nthr) {
-      const int t = i / per_t;
-      const int g = i - t * per_t;
-      chain_item(W + (t << logn), logn, p, g);
-    }
-    sync();
-  }
-}
-
-// Everything between fold and combine for T transforms of 2^logn cells.
-template <int MAXI, class Sync, typename WP>
-QFT_HD void mid_sweeps(WP W, int logn, int T, const float* sec, int tid, int nthr, Sync sync) {
-  if (logn >= 3) {
-    forward_sweep(W, logn - 1, 2 * T, SIDES_ALT, logn - 2, 1, true, sec, tid, nthr, sync);
-    backward_sweep<MAXI>(W, logn - 1, 2 * T, SIDES_ALT, 1, logn - 2, true, tid, nthr, sync);
-  }
-  chain_sweep(W, logn, T, 1, logn, tid, nthr, sync);
-}
-
-// ===========================================================================
-// Register-blocked sweeps.  CPT = cells per thread of the workgroup buffer
-// (buffer cells / threads, compile time) bounds the registers each thread
-// holds across the load/store barrier of a backward chunk.
-// ===========================================================================
-// Forward rounds S = 2^hi .. 2^(hi-K+1), G = 2^(hi-K) >= 2 (in place).
-template <int K, int CPT, typename WP>
-QFT_HD void fwd_chunk2(WP W, int lgside, int nsides, int mode, int hi, bool skip0,
-                       const float* sec, int tid, int nthr) {
-  constexpr int NI = (CPT + (2 << K) - 1) / (2 << K);  // groups per thread
-  const int lgGroups = lgside - K - 1;
-  const int total = nsides << lgGroups;
-  const int lgHalfG = hi - K - 1;
-#pragma unroll
-  for (int it = 0; it < NI; ++it) {
-    const int i = tid + it * nthr;
-    if (i < total) {
-      const int s = i >> lgGroups;
-      const int g = i & ((1 << lgGroups) - 1);
-      const int j = g >> lgHalfG;
-      const int x = g & ((1 << lgHalfG) - 1);
-      auto sd = W + (s << lgside);
-      if (side_is_dst(mode, s)) fwd_group<K, true>(sd, 1 << hi, j, x, sec, skip0);
-      else fwd_group<K, false>(sd, 1 << hi, j, x, sec, skip0);
-    }
-  }
-}
-
-// Fused innermost rounds on whole segments of 2^K cells (in place).
-template <int K, int CPT, typename WP>
-QFT_HD void tail_chunk(WP W, int lgside, int nsides, int mode, bool skip0, const float* sec,
-                       int tid, int nthr) {
-  constexpr int NI = (CPT + (1 << K) - 1) / (1 << K);  // segments per thread
-  const int lgGroups = lgside - K;
-  const int total = nsides << lgGroups;
-#pragma unroll
-  for (int it = 0; it < NI; ++it) {
-    const int i = tid + it * nthr;
-    if (i >= total) break;
-    const int s = i >> lgGroups;
-    const int g = i & ((1 << lgGroups) - 1);
-    auto sd = W + (s << lgside);
-    if (side_is_dst(mode, s)) tail_group<K, true>(sd, g, sec, skip0);
-    else tail_group<K, false>(sd, g, sec, skip0);
-  }
-}
-
-// K backward rounds S = 2^lo .. 2^(lo+K-1): load, barrier, store, barrier.
-template <int K, int CPT, class Sync, typename WP>
-QFT_HD void bwd_chunk2(WP W, int lgside, int nsides, int mode, int lo, bool skip0, int tid,
-                       int nthr, Sync sync) {
-  constexpr int R = 1 << K;
-  constexpr int MAXG = (CPT >> K) > 0 ? (CPT >> K) : 1;
-  const int S = 1 << (lo + K - 1);
-  const int lgG = lo - 1;
-  const int lgGroups = lgside - K;  // thread groups (j, i) per side
-  const int total = nsides << lgGroups;
-  float2 y[MAXG][R];
-#pragma unroll
-  for (int it = 0; it < MAXG; ++it) {
-    const int i = tid + it * nthr;
-    if (i < total) {
-      const int s = i >> lgGroups;
-      const int g = i & ((1 << lgGroups) - 1);
-      const int j = g >> lgG, ii = g & ((1 << lgG) - 1);
-      auto sd = W + (s << lgside);
-      const bool dst = side_is_dst(mode, s);
-      if (skip0 && j == 0) {
-        if (dst) bwd_head_load<K, true, 1>(sd, 1 << lgG, ii, y[it]);
-        else bwd_head_load<K, false, 1>(sd, 1 << lgG, ii, y[it]);
-      } else {
-        if (dst) bwd_group_load<K, true>(sd, S, j, ii, y[it]);
-        else bwd_group_load<K, false>(sd, S, j, ii, y[it]);
-      }
-    }
-  }
-  sync();
-#pragma unroll
-  for (int it = 0; it < MAXG; ++it) {
-    const int i = tid + it * nthr;
-    if (i < total) {
-      const int s = i >> lgGroups;
-      const int g = i & ((1 << lgGroups) - 1);
-      const int j = g >> lgG, ii = g & ((1 << lgG) - 1);
-      auto sd = W + (s << lgside);
-      if (skip0 && j == 0) {
-        bwd_head_store<K, 1>(sd, 1 << lgG, ii, y[it]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < R; ++e) sd[j * S + ii * R + e] = y[it][e];
-      }
-    }
-  }
-  sync();
-}
-
-// Forward rounds S = 2^top .. 2^1 and backward rounds back up, with the
-// innermost KT rounds fused in registers and the others in chunks of <= 3.
-template <int CPT, class Sync, typename WP>
-QFT_HD void sweeps2(WP W, int lgside, int nsides, int mode, int top, bool skip0,
-                    const float* sec, int tid, int nthr, Sync sync) {
-  constexpr int KT = 3, KC = 3;
-  if (top < 1) return;
-  const int kt = top < KT ? top : KT;
-  // forward chunks above the tail, from the top: rounds (kt, top]
-  for (int hi = top; hi > kt;) {
-    const int K = (hi - kt) < KC ? (hi - kt) : KC;
-    if (K == 3) fwd_chunk2<3, CPT>(W, lgside, nsides, mode, hi, skip0, sec, tid, nthr);
-    else if (K == 2) fwd_chunk2<2, CPT>(W, lgside, nsides, mode, hi, skip0, sec, tid, nthr);
-    else fwd_chunk2<1, CPT>(W, lgside, nsides, mode, hi, skip0, sec, tid, nthr);
-    sync();
-    hi -= K;
-  }
-  if (kt == 3) tail_chunk<3, CPT>(W, lgside, nsides, mode, skip0, sec, tid, nthr);
-  else if (kt == 2) tail_chunk<2, CPT>(W, lgside, nsides, mode, skip0, sec, tid, nthr);
-  else tail_chunk<1, CPT>(W, lgside, nsides, mode, skip0, sec, tid, nthr);
-  sync();
-  // backward chunks above the tail, from the bottom: rounds (kt, top]
-  for (int lo = kt + 1; lo <= top;) {
-    const int K = (top - lo + 1) < KC ? (top - lo + 1) : KC;
-    if (K == 3) bwd_chunk2<3, CPT>(W, lgside, nsides, mode, lo, skip0, tid, nthr, sync);
-    else if (K == 2) bwd_chunk2<2, CPT>(W, lgside, nsides, mode, lo, skip0, tid, nthr, sync);
-    else bwd_chunk2<1, CPT>(W, lgside, nsides, mode, lo, skip0, tid, nthr, sync);
-    lo += K;
-  }
-}
-
-// Chain levels P = 2 .. 2^logn for T transforms.  Levels up to 2^pw run
-// wave-synchronously (one wave per transform, `wsync` orders its LDS
-// accesses); the larger levels are one block-synchronised pass each.
-template <class Sync, class WSync, typename WP>
-QFT_HD void chain2(WP W, int logn, int T, int tid, int nthr, int wave_size, Sync sync,
-                   WSync wsync) {
-  constexpr int PW = 9;
-  const int pw = logn < PW ? logn : PW;
-  const int nwaves = (nthr + wave_size - 1) / wave_size;
-  const int wave = tid / wave_size, lane = tid - wave * wave_size;
-  const int wlanes = (nthr - wave * wave_size) < wave_size ? (nthr - wave * wave_size) : wave_size;
-  const int rounds = (T + nwaves - 1) / nwaves;
-  for (int r = 0; r < rounds; ++r) {
-    const int t = wave + r * nwaves;
-    for (int p = 1; p <= pw; ++p) {
-      if (t < T) {
-        const int per_t = chain_groups(p);
-        for (int g = lane; g < per_t; g += wlanes) chain_item(W + (t << logn), logn, p, g);
-      }
-      wsync();
-    }
-  }
-  sync();
-  for (int p = pw + 1; p <= logn; ++p) {
-    const int per_t = chain_groups(p);
-    const int total = T * per_t;
-    for (int i = tid; i < total; i += nthr) {
-      const int t = i / per_t;
-      const int g = i - t * per_t;
-      chain_item(W + (t << logn), logn, p, g);
-    }
-    sync();
-  }
-}
-
-// Everything between fold and combine for T transforms of 2^logn cells.
-template <int CPT, class Sync, class WSync, typename WP>
-QFT_HD void mid_sweeps2(WP W, int logn, int T, const float* sec, int tid, int nthr,
-                        int wave_size, Sync sync, WSync wsync) {
-  if (logn >= 3) sweeps2<CPT>(W, logn - 1, 2 * T, SIDES_ALT, logn - 2, true, sec, tid, nthr, sync);
-  chain2(W, logn, T, tid, nthr, wave_size, sync, wsync);
-}
-
-// ===========================================================================
-// Whole-transform work of one workgroup: T transforms of length 2^logn.
-// Transform t is read from x + off(t) and written to X + off(t), with
-// off(t) = offs[t] when offs is given, else t * 2^logn.
-// ===========================================================================
-template <int DT, bool SWAP, int CPT, class Sync, class WSync, typename WP>
-QFT_HD void tile_body(const typename Store<DT>::T* x, typename Store<DT>::T* X, WP W, int logn,
-                      int T, const int64_t* offs, const float* sec, int tid, int nthr,
-                      int wave_size, Sync sync, WSync wsync) {
-  // every thread owns at most FI fold/combine items (cell pairs); all global
-  // loads of a thread are issued before the first use so they overlap
-  constexpr int FI = (CPT + 1) / 2;
-  const int n = 1 << logn, h = n >> 1;
-  const int total = T << (logn - 1);
-  float2 av[FI], bv[FI];
-#pragma unroll
-  for (int it = 0; it < FI; ++it) {
-    const int i = tid + it * nthr;
-    if (i < total) {
-      const int t = i >> (logn - 1);
-      const int m = i & (h - 1);
-      const int64_t o = offs ? offs[t] : ((int64_t)t << logn);
-      const typename Store<DT>::T* xt = x + o;
-      av[it] = Store<DT>::ld(xt, m);
-      bv[it] = Store<DT>::ld(xt, m == 0 ? h : n - m);
-    }
-  }
-#pragma unroll
-  for (int it = 0; it < FI; ++it) {
-    const int i = tid + it * nthr;
-    if (i < total) {
-      const int t = i >> (logn - 1);
-      const int m = i & (h - 1);
-      auto w = W + (t << logn);
-      const float2 a = sw<SWAP>(av[it]), b = sw<SWAP>(bv[it]);
-      if (m == 0) {
-        w[0] = a;  // c(0)
-        w[h] = b;  // c(N/2)
-      } else {
-        const int l = __builtin_ctz(m);
-        const int cell = (n >> (l + 2)) + (m >> (l + 1));
-        w[cell] = cadd(a, b);
-        w[h + cell] = csub(a, b);
-      }
-    }
-  }
-  sync();
-  mid_sweeps2<CPT>(W, logn, T, sec, tid, nthr, wave_size, sync, wsync);
-#pragma unroll
-  for (int it = 0; it < FI; ++it) {
-    const int i = tid + it * nthr;
-    if (i < total) {
-      const int t = i >> (logn - 1);
-      const int k = i & (h - 1);
-      const int64_t o = offs ? offs[t] : ((int64_t)t << logn);
-      typename Store<DT>::T* Xt = X + o;
-      auto w = W + (t << logn);
-      if (k == 0) {
-        Store<DT>::st(Xt, 0, sw<SWAP>(w[0]));
-        Store<DT>::st(Xt, h, sw<SWAP>(w[h]));
-      } else {
-        const float2 C = w[k], S = w[h + k];
-        Store<DT>::st(Xt, k, sw<SWAP>(make_float2(C.x + S.y, C.y - S.x)));
-        Store<DT>::st(Xt, n - k, sw<SWAP>(make_float2(C.x - S.y, C.y + S.x)));
-      }
-    }
-  }
 }
 
 // ===========================================================================

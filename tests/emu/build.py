@@ -31,14 +31,13 @@ def load():
     import ctypes
     L = ctypes.CDLL(build(force=False))
     i, vp, i64 = ctypes.c_int, ctypes.c_void_p, ctypes.c_int64
-    L.emu_tile.argtypes = [i, i, vp, vp, i, i, i]
     L.emu_multipass.argtypes = [i, i, vp, vp, i, i64, i, i]
-    L.emu_uneven.argtypes = [i, i, vp, vp, ctypes.POINTER(ctypes.c_int32), i64, i, i, i]
+    L.emu_uneven.argtypes = [i, i, vp, vp, ctypes.POINTER(ctypes.c_int32), i64, i, i]
     L.emu_twopass.argtypes = [i, i, vp, vp, i, i64]
     L.emu_tile_s.argtypes = [i, i, vp, vp, i, i, vp]
     L.emu_tile_real.argtypes = [i, i, i, i64, vp, vp, vp, vp]
     L.emu_multipass_real.argtypes = [i, i, i, i64, vp, vp, vp, vp, i, i]
-    for f in (L.emu_tile, L.emu_multipass, L.emu_uneven, L.emu_twopass, L.emu_tile_s,
+    for f in (L.emu_multipass, L.emu_uneven, L.emu_twopass, L.emu_tile_s,
               L.emu_tile_real, L.emu_multipass_real):
         f.restype = i
     return L

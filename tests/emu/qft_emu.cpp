@@ -150,8 +150,6 @@ void run_workgroup(int nthr, Tracker& tr, F fn) {
   tr.end_phase();
 }
 
-constexpr int kEmuCpt = 256;  // cells per emulated thread bound (register arrays)
-constexpr int kEmuWave = 32;  // emulated wavefront width (wave-level chain phase)
 
 // The specialised tile kernel exactly as launched on the GPU: LOGN <= 12 uses
 // 2^12-cell tiles of 256 threads, 13 uses 512 threads, 14 uses 1024.
@@ -240,22 +238,6 @@ int tile_s_dispatch(const void* x, void* X, int logn, int Tact, const float* sec
     case 14: return tile_s_impl<DT, SWAP, 14>(x, X, Tact, sec, offs);
     default: return -1;
   }
-}
-
-template <int DT, bool SWAP>
-int tile_impl(const void* x, void* X, int logn, int T, const int64_t* offs, const float* sec,
-              int nthr) {
-  using E = typename qftk::Store<DT>::T;
-  const int64_t cells = (int64_t)T << logn;
-  if ((cells + nthr - 1) / nthr > kEmuCpt) return -2;
-  std::vector<float2> lds(cells + (cells >> kEmuPad));
-  Tracker tr(nthr);
-  TPtr W{lds.data(), 0, &tr, cells, kEmuPad};
-  run_workgroup(nthr, tr, [&](int tid, auto sync) {
-    qftk::tile_body<DT, SWAP, kEmuCpt>((const E*)x, (E*)X, W, logn, T, offs, sec, tid, nthr,
-                                       kEmuWave, sync, sync);
-  });
-  return tr.oob ? -100 : (int)tr.races;
 }
 
 std::vector<float> secants(int lg) {
@@ -427,25 +409,34 @@ int multipass_real_impl(int kind, int logn, int64_t rows, const void* in0, const
       slots, seg_log2, nthr, sec);
 }
 
+// Uneven packed batch as the library runs it: transforms of up to 2^12
+// points in 2^12-cell tiles of the size-sorted work list, 2^13 and 2^14 in a
+// tile of their own (the persistent kernel's larger tile sizes), all through
+// the specialised tile kernel with the offset list; longer ones through the
+// multi-pass schedule (segments of 2^seg_log2 cells).
 template <int DT, bool SWAP>
-int uneven_impl(const void* x, void* X, const int32_t* log2n, int64_t count, int tile_log2,
-                int seg_log2, int nthr) {
+int uneven_impl(const void* x, void* X, const int32_t* log2n, int64_t count, int seg_log2,
+                int nthr) {
   using E = typename qftk::Store<DT>::T;
   int mx = 3;
   for (int64_t i = 0; i < count; ++i) mx = mx > log2n[i] ? mx : log2n[i];
   std::vector<float> sec = secants(mx);
   std::vector<int64_t> off, perm, large;
   std::vector<qftk::TileDesc> tiles;
-  qftk::build_uneven_worklist(log2n, count, tile_log2, off, tiles, perm, large);
+  qftk::build_uneven_worklist(log2n, count, 12, off, tiles, perm, large);
   int races = 0;
   for (const auto& d : tiles) {
-    int r = tile_impl<DT, SWAP>(x, X, d.log2n, d.count, perm.data() + d.first, sec.data(), nthr);
+    const int r =
+        tile_s_dispatch<DT, SWAP>(x, X, d.log2n, d.count, sec.data(), perm.data() + d.first);
     if (r < 0) return r;
     races += r;
   }
   for (int64_t i : large) {
-    int r = multipass_impl<DT, SWAP>((const E*)x + off[i], (E*)X + off[i], log2n[i], 1, seg_log2,
-                                     nthr, sec.data());
+    const int r =
+        log2n[i] <= 14
+            ? tile_s_dispatch<DT, SWAP>(x, X, log2n[i], 1, sec.data(), off.data() + i)
+            : multipass_impl<DT, SWAP>((const E*)x + off[i], (E*)X + off[i], log2n[i], 1,
+                                       seg_log2, nthr, sec.data());
     if (r < 0) return r;
     races += r;
   }
@@ -531,15 +522,6 @@ int emu_twopass(int dt, int swap, const void* x, void* X, int mc_log2, int64_t b
 }
 
 
-int emu_tile(int dt, int swap, const void* x, void* X, int logn, int T, int nthr) {
-  if (logn < 1 || logn > 14 || T < 1 || nthr < 1) return -1;
-  std::vector<float> sec = secants(logn);
-  if (dt == 0) return swap ? tile_impl<0, true>(x, X, logn, T, nullptr, sec.data(), nthr)
-                           : tile_impl<0, false>(x, X, logn, T, nullptr, sec.data(), nthr);
-  return swap ? tile_impl<1, true>(x, X, logn, T, nullptr, sec.data(), nthr)
-              : tile_impl<1, false>(x, X, logn, T, nullptr, sec.data(), nthr);
-}
-
 // One workgroup of the specialised GPU tile kernel (Tact transforms): a
 // contiguous batch, or, with offs != NULL, transforms at element offsets
 // offs[0 .. Tact) (the persistent kernel of uneven plans).
@@ -586,12 +568,12 @@ int emu_multipass(int dt, int swap, const void* x, void* X, int logn, int64_t ba
 }
 
 int emu_uneven(int dt, int swap, const void* x, void* X, const int32_t* log2n, int64_t count,
-               int tile_log2, int seg_log2, int nthr) {
+               int seg_log2, int nthr) {
   if (count < 1 || nthr < 1) return -1;
-  if (dt == 0) return swap ? uneven_impl<0, true>(x, X, log2n, count, tile_log2, seg_log2, nthr)
-                           : uneven_impl<0, false>(x, X, log2n, count, tile_log2, seg_log2, nthr);
-  return swap ? uneven_impl<1, true>(x, X, log2n, count, tile_log2, seg_log2, nthr)
-              : uneven_impl<1, false>(x, X, log2n, count, tile_log2, seg_log2, nthr);
+  if (dt == 0) return swap ? uneven_impl<0, true>(x, X, log2n, count, seg_log2, nthr)
+                           : uneven_impl<0, false>(x, X, log2n, count, seg_log2, nthr);
+  return swap ? uneven_impl<1, true>(x, X, log2n, count, seg_log2, nthr)
+              : uneven_impl<1, false>(x, X, log2n, count, seg_log2, nthr);
 }
 
 }  // extern "C"

@@ -11,6 +11,8 @@ schedules (with small segment sizes, so that many passes occur at small N).
 Tolerance: FP32 arithmetic, relative RMS error (eq. qft_44 per signal)
 <= 1e-5 * log2 N against the FP64 oracle run on the FP32-rounded input.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -40,58 +42,6 @@ def _ref(x64, swap=False):
         X = OB.cdft(np.conj(x) if swap else x)
         return np.conj(X) if swap else X
     return Q.qft_adjoint(x) if swap else Q.qft(x)
-
-
-def run_tile(emu, x, nthr=64, swap=0):
-    xf = _as_c64(x)
-    out = np.zeros_like(xf)
-    T, N = xf.shape
-    races = emu.emu_tile(0, swap, xf.ctypes.data, out.ctypes.data, N.bit_length() - 1, T, nthr)
-    assert races >= 0, races
-    return races, out
-
-
-@pytest.mark.parametrize("logn", range(1, 13))
-def test_tile_all_sizes(emu, logn):
-    N = 1 << logn
-    T = max(1, min(4, 4096 // N))
-    x = workloads.uniform(100 + logn, (T, N))
-    races, out = run_tile(emu, x)
-    assert races == 0
-    err = D.relative_l2(out, _ref(x))
-    assert err.max() <= _tol(logn), err.max()
-
-
-@pytest.mark.parametrize("logn,T,nthr", [(10, 4, 256), (12, 1, 256), (13, 1, 512), (8, 3, 64),
-                                          (5, 7, 32)])
-def test_tile_block_shapes_and_ragged(emu, logn, T, nthr):
-    """Real block sizes of the tile kernel, and a ragged last tile (T below
-    the tile capacity)."""
-    x = workloads.normal(7, (T, 1 << logn))
-    races, out = run_tile(emu, x, nthr=nthr)
-    assert races == 0
-    assert D.relative_l2(out, _ref(x)).max() <= _tol(logn)
-
-
-@pytest.mark.parametrize("logn", [1, 2, 3, 7, 11])
-def test_tile_adjoint(emu, logn):
-    x = workloads.uniform(9, (2, 1 << logn))
-    races, out = run_tile(emu, x, swap=1)
-    assert races == 0
-    assert D.relative_l2(out, _ref(x, swap=True)).max() <= _tol(logn)
-
-
-def test_tile_fp16_storage(emu):
-    logn, T = 9, 8
-    x = workloads.uniform(12, (T, 1 << logn))
-    x16 = np.stack([x.real, x.imag], -1).astype(np.float16)
-    out = np.zeros_like(x16)
-    races = emu.emu_tile(1, 0, x16.ctypes.data, out.ctypes.data, logn, T, 64)
-    assert races == 0
-    xin = x16[..., 0].astype(np.float64) + 1j * x16[..., 1].astype(np.float64)
-    got = out[..., 0].astype(np.float64) + 1j * out[..., 1].astype(np.float64)
-    # output rounding to FP16 dominates: ~2^-11 relative
-    assert D.relative_l2(got, Q.qft(xin)).max() < 1e-3
 
 
 def run_mp(emu, x, seg, nthr=16, swap=0):
@@ -136,19 +86,20 @@ def test_multipass_library_segment_size(emu):
 
 
 def test_uneven_worklist(emu):
-    """Packed uneven batch: small tiles (2^7 cells) so that several sizes share
-    the work list, and two transforms beyond the tile size go multi-pass
-    (segments of 2^3)."""
+    """Packed uneven batch as the library runs it: sizes up to 2^12 share
+    2^12-cell tiles of the size-sorted work list, 2^13 and 2^14 take a tile of
+    their own, all through the specialised tile kernel and the offset list;
+    2^15 goes multi-pass (segments of 2^3)."""
     rng = np.random.default_rng(3)
-    log2n = np.array(list(rng.integers(1, 8, 40)) + [9, 10], dtype=np.int32)
+    log2n = np.array(list(rng.integers(1, 13, 40)) + [13, 14, 15], dtype=np.int32)
     rng.shuffle(log2n)
     total = int(np.sum(1 << log2n.astype(np.int64)))
     vals = workloads.uniform(21, (total,))
     xf = _as_c64(vals)
     out = np.zeros_like(xf)
     races = emu.emu_uneven(0, 0, xf.ctypes.data, out.ctypes.data,
-                           log2n.ctypes.data_as(__import__("ctypes").POINTER(
-                               __import__("ctypes").c_int32)), log2n.size, 7, 3, 16)
+                           log2n.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), log2n.size,
+                           3, 16)
     assert races == 0
     off = 0
     for r in log2n:
