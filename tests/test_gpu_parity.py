@@ -65,11 +65,13 @@ def test_all_tile_sizes(logn):
     assert err.max() <= tol(logn), err.max()
 
 
-@pytest.mark.parametrize("logn,B", [(15, 3), (16, 2), (17, 2), (18, 1), (19, 1), (20, 2),
-                                    (21, 1), (22, 1), (23, 1)])
+@pytest.mark.parametrize("logn,B", [(15, 3), (16, 2), (15, 200), (16, 130), (17, 2), (18, 1),
+                                    (19, 1), (20, 2), (21, 1), (22, 1), (23, 1)])
 def test_multipass_sizes(logn, B):
-    """Two-pass (2^15, 2^16) and multi-pass sizes: every split of the global
-    rounds and chain levels into passes of 3 to 5 that the library uses."""
+    """Two-pass (2^15, 2^16, including batches that leave the last group of
+    eight transforms of pass A ragged) and multi-pass sizes: every split of
+    the global rounds and chain levels into passes of 3 to 5 that the library
+    uses."""
     say(f"multi-pass: N=2^{logn} B={B}")
     x = workloads.normal(2000 + logn, (B, 1 << logn))
     err = D.relative_l2(gpu_fwd(x), ref_fwd(x))
@@ -286,6 +288,7 @@ def test_graph_capture_replays(kind):
     elif kind == "two_pass":
         x = torch.from_numpy(workloads.normal(77, (8, 1 << 16))).to(DEV)
         plan = qft.Plan(16, 8)
+
     else:
         x = torch.from_numpy(workloads.uniform(78, (64, 1 << 10))).to(DEV)
         plan = qft.Plan(10, 64)
