@@ -1,12 +1,12 @@
 """Builds the gfx950 library ``libqft.so`` in-tree.
 
-Fifteen translation units compile in parallel (at most MAX_JOBS or one per
-CPU at a time) and link into one shared library: ``csrc/qft_lib.hip``
+Twenty-three translation units compile in parallel (at most MAX_JOBS or one
+per CPU at a time) and link into one shared library: ``csrc/qft_lib.hip``
 (plans, C ABI, two-pass kernels), ``csrc/qft_multipass.hip`` once per
 storage type (``-DQFT_MP_DT=0`` complex FP32, ``=1`` complex FP16) and
 ``csrc/qft_tiles.hip`` once per storage type (``-DQFT_TILE_DT``), tile size
-(``-DQFT_TILE_TL=12, 13, 14``) and direction (``-DQFT_TILE_SWAP=0``
-forward, ``=1`` adjoint).
+(``-DQFT_TILE_TL=10 .. 14``) and direction (``-DQFT_TILE_SWAP=0`` forward,
+``=1`` adjoint).
 
 Flags: ``--offload-arch=gfx950 -O3`` and packed FP32 instructions disabled
 (``-Xclang -target-feature -Xclang -packed-fp32-ops``; the host pass warns
@@ -48,7 +48,7 @@ def build(verbose=False):
     with tempfile.TemporaryDirectory(prefix="qft_build_") as tmp:
         units = [(TILES, ["-DQFT_TILE_DT=%d" % dt, "-DQFT_TILE_TL=%d" % tl,
                           "-DQFT_TILE_SWAP=%d" % sw], "tiles_%d_%d_%d.o" % (dt, tl, sw))
-                 for tl in (14, 13, 12) for dt in (0, 1) for sw in (0, 1)]
+                 for tl in (14, 13, 12, 11, 10) for dt in (0, 1) for sw in (0, 1)]
         units[0:0] = [(SRC, [], "lib.o")] + [
             (MULTI, ["-DQFT_MP_DT=%d" % dt], "multipass_%d.o" % dt) for dt in (0, 1)]
         # at most one compiler per CPU (each takes ~1-2 GB)

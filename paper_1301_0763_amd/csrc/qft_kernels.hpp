@@ -32,18 +32,21 @@ constexpr int kWave = 64;
 // alternate between the two halves of the banks.
 constexpr int kPad = 4;
 
-// Persistent tile kernel with tiles of 2^tl cells (12 <= tl <= 14): 16 cells
-// per thread, and as many resident workgroups per CU as the LDS allows
-// (2^tl padded float2 cells out of 160 KiB).
-constexpr int kMinTileLog2 = 12;
+// Tile kernels with tiles of 2^tl cells (10 <= tl <= 14): 16 cells per
+// thread (64 to 1024 threads), and as many resident workgroups per CU as the
+// LDS (2^tl padded float2 cells out of 160 KiB) and the four waves per SIMD
+// of the persistent kernel allow.
+constexpr int kMinTileLog2 = 10;
 constexpr int kMaxTileLog2 = 14;
 constexpr int tile_threads(int tl) { return (1 << tl) / 16; }
-constexpr int tile_wgs_per_cu(int tl) { return tl <= 12 ? 4 : (tl == 13 ? 2 : 1); }
+constexpr int tile_wgs_per_cu(int tl) {
+  return tl <= 10 ? 16 : (tl == 11 ? 8 : (tl == 12 ? 4 : (tl == 13 ? 2 : 1)));
+}
 
 // One tile-kernel launch.  Uniform groups (d_tiles == nullptr): a
 // contiguous batch of `ubatch` transforms of 2^ulog2n points in tiles of
 // T = 2^(tl - ulog2n) transforms (the last one ragged), one workgroup per
-// tile (tl = max(12, ulog2n)).  Uneven groups: tile w = (log2n, first,
+// tile (tl = max(10, ulog2n)).  Uneven groups: tile w = (log2n, first,
 // count, 0) holds `count` transforms of 2^log2n points at element offsets
 // d_offs[first .. first + count); `grid` workgroups stride over the tiles
 // (grid = ntiles: one workgroup per tile) and exit after their last one.

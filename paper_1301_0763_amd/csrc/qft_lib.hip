@@ -278,6 +278,8 @@ qft_status run_schedule(const qft_plan_s* p, const Schedule& s, const void* in, 
     if (g.ntiles == 0) continue;
     hipError_t e = hipErrorInvalidValue;
     switch (g.tl) {
+      case 10: e = qftk::launch_tiles<DT, 10, SWAP>(g, in, out, p->d_sec, st); break;
+      case 11: e = qftk::launch_tiles<DT, 11, SWAP>(g, in, out, p->d_sec, st); break;
       case 12: e = qftk::launch_tiles<DT, 12, SWAP>(g, in, out, p->d_sec, st); break;
       case 13: e = qftk::launch_tiles<DT, 13, SWAP>(g, in, out, p->d_sec, st); break;
       case 14: e = qftk::launch_tiles<DT, 14, SWAP>(g, in, out, p->d_sec, st); break;
@@ -344,6 +346,10 @@ qft_status run_real(const qft_plan_s* p, int kind, const qftk::RealArgs& a, hipS
   hipError_t e = hipErrorInvalidValue;
   const bool h16 = p->dtype == QFT_C16;
   switch (g.tl) {
+    case 10: e = h16 ? qftk::launch_real<1, 10>(g, kind, a, p->d_sec, st)
+                     : qftk::launch_real<0, 10>(g, kind, a, p->d_sec, st); break;
+    case 11: e = h16 ? qftk::launch_real<1, 11>(g, kind, a, p->d_sec, st)
+                     : qftk::launch_real<0, 11>(g, kind, a, p->d_sec, st); break;
     case 12: e = h16 ? qftk::launch_real<1, 12>(g, kind, a, p->d_sec, st)
                      : qftk::launch_real<0, 12>(g, kind, a, p->d_sec, st); break;
     case 13: e = h16 ? qftk::launch_real<1, 13>(g, kind, a, p->d_sec, st)
@@ -414,8 +420,7 @@ qft_status qft_plan_create(qft_plan_t* plan, int log2n, int64_t batch, qft_dtype
   p->max_log2n = log2n;
   add_costs(p, log2n, batch);
   if (log2n <= qftk::kMaxTileLog2) {
-    // one schedule per tile size that holds a transform; the smallest first
-    // one workgroup per tile of 2^max(12, log2n) cells
+    // one workgroup per tile of 2^max(10, log2n) cells
     const int tl = std::max(qftk::kMinTileLog2, log2n);
     Schedule sc;
     sc.name = "t" + std::to_string(tl) + ":" + std::to_string(log2n);
@@ -475,16 +480,19 @@ qft_status qft_plan_create_uneven(qft_plan_t* plan, const int32_t* log2n, int64_
     p->large.push_back({log2n[i], off[i], 1});
     p->work_cells = std::max<int64_t>(p->work_cells, (int64_t)1 << log2n[i]);
   }
-  // Candidate schedules: tile size for N <= 2^12, for 2^13 and for 2^14; sizes
-  // with the same tile size share one launch.  Each comes with a resident
-  // (persistent) grid and, as "<name>/all", with one workgroup per tile.  The
-  // first one runs every N <= 2^14 in a single persistent launch.
-  const int cand[4][3] = {{14, 14, 14}, {13, 13, 14}, {12, 14, 14}, {12, 13, 14}};
+  // Candidate schedules: tile size for N <= 2^10, 2^11, 2^12, 2^13 and 2^14;
+  // sizes with the same tile size share one launch.  Each comes with a
+  // resident (persistent) grid and, as "<name>/all", with one workgroup per
+  // tile.  The first one runs every N <= 2^14 in a single persistent launch.
+  constexpr int kCand = 7;
+  const int cand[kCand][5] = {{14, 14, 14, 14, 14}, {13, 13, 13, 13, 14}, {12, 12, 12, 14, 14},
+                              {12, 12, 12, 13, 14}, {10, 11, 12, 13, 14}, {10, 11, 12, 14, 14},
+                              {10, 12, 12, 13, 14}};
   std::vector<Schedule> persistent;
-  for (int c = 0; c < 4 && s == QFT_SUCCESS; ++c) {
+  for (int c = 0; c < kCand && s == QFT_SUCCESS; ++c) {
     int tl_of[qftk::kMaxTileLog2 + 1];
     for (int r = 1; r <= qftk::kMaxTileLog2; ++r)
-      tl_of[r] = r <= 12 ? cand[c][0] : (r == 13 ? cand[c][1] : cand[c][2]);
+      tl_of[r] = cand[c][r <= 10 ? 0 : r - 10];
     // launches: maximal runs of present sizes with the same tile size
     std::vector<int> lo_hi;
     std::string name;

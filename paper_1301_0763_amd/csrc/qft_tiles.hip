@@ -1,7 +1,7 @@
 // Tile kernels (transforms of N <= 2^14 points, whole transforms in one
 // workgroup's LDS).  Built once per storage type QFT_TILE_DT (0: complex
 // FP32, 1: complex FP16 storage with FP32 arithmetic), tile size
-// 2^QFT_TILE_TL (12, 13, 14) and direction QFT_TILE_SWAP (0: forward, 1:
+// 2^QFT_TILE_TL (10 .. 14) and direction QFT_TILE_SWAP (0: forward, 1:
 // adjoint), each combination a translation unit of its own so that they
 // compile in parallel.
 //
@@ -15,7 +15,7 @@
 #include "qft_kernels.hpp"
 
 #if !defined(QFT_TILE_DT) || !defined(QFT_TILE_TL) || !defined(QFT_TILE_SWAP)
-#error "QFT_TILE_DT (0, 1), QFT_TILE_TL (12, 13, 14) and QFT_TILE_SWAP (0, 1) must be defined"
+#error "QFT_TILE_DT (0, 1), QFT_TILE_TL (10 .. 14) and QFT_TILE_SWAP (0, 1) must be defined"
 #endif
 
 namespace qftk {

@@ -151,13 +151,14 @@ void run_workgroup(int nthr, Tracker& tr, F fn) {
 }
 
 
-// The specialised tile kernel exactly as launched on the GPU: LOGN <= 12 uses
-// 2^12-cell tiles of 256 threads, 13 uses 512 threads, 14 uses 1024.
+// The specialised tile kernel exactly as launched on the GPU: LOGN <= 10 uses
+// 2^10-cell tiles of 64 threads, larger LOGN a tile of 2^LOGN cells with 16
+// cells per thread (128 .. 1024 threads).
 template <int DT, bool SWAP, int LOGN>
 int tile_s_impl(const void* x, void* X, int Tact, const float* sec, const int64_t* offs) {
   using E = typename qftk::Store<DT>::T;
-  constexpr int TL = LOGN <= 12 ? 12 : LOGN;
-  constexpr int NT = TL == 12 ? 256 : (TL == 13 ? 512 : 1024);
+  constexpr int TL = LOGN <= 10 ? 10 : LOGN;
+  constexpr int NT = (1 << TL) / 16;
   constexpr int T = 1 << (TL - LOGN);
   if (Tact < 1 || Tact > T) return -2;
   const int64_t cells = (int64_t)T << LOGN;
@@ -183,8 +184,8 @@ int tile_real_impl(int64_t rows, const void* in0, const void* in1, void* out0, v
                    const float* sec) {
   using R = typename qftk::RStore<DT>::T;
   using E = typename qftk::Store<DT>::T;
-  constexpr int TL = LOGN <= 12 ? 12 : LOGN;
-  constexpr int NT = TL == 12 ? 256 : (TL == 13 ? 512 : 1024);
+  constexpr int TL = LOGN <= 10 ? 10 : LOGN;
+  constexpr int NT = (1 << TL) / 16;
   constexpr int T = 1 << (TL - LOGN);
   const int slots = (int)((rows + 1) / 2);
   if (rows < 1 || slots > T) return -2;
@@ -409,8 +410,8 @@ int multipass_real_impl(int kind, int logn, int64_t rows, const void* in0, const
       slots, seg_log2, nthr, sec);
 }
 
-// Uneven packed batch as the library runs it: transforms of up to 2^12
-// points in 2^12-cell tiles of the size-sorted work list, 2^13 and 2^14 in a
+// Uneven packed batch as the library runs it: transforms of up to 2^10
+// points in 2^10-cell tiles of the size-sorted work list, 2^11 .. 2^14 in a
 // tile of their own (the persistent kernel's larger tile sizes), all through
 // the specialised tile kernel with the offset list; longer ones through the
 // multi-pass schedule (segments of 2^seg_log2 cells).
@@ -423,7 +424,7 @@ int uneven_impl(const void* x, void* X, const int32_t* log2n, int64_t count, int
   std::vector<float> sec = secants(mx);
   std::vector<int64_t> off, perm, large;
   std::vector<qftk::TileDesc> tiles;
-  qftk::build_uneven_worklist(log2n, count, 12, off, tiles, perm, large);
+  qftk::build_uneven_worklist(log2n, count, 10, off, tiles, perm, large);
   int races = 0;
   for (const auto& d : tiles) {
     const int r =

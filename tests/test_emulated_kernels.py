@@ -86,8 +86,8 @@ def test_multipass_library_segment_size(emu):
 
 
 def test_uneven_worklist(emu):
-    """Packed uneven batch as the library runs it: sizes up to 2^12 share
-    2^12-cell tiles of the size-sorted work list, 2^13 and 2^14 take a tile of
+    """Packed uneven batch as the library runs it: sizes up to 2^10 share
+    2^10-cell tiles of the size-sorted work list, 2^11 .. 2^14 take a tile of
     their own, all through the specialised tile kernel and the offset list;
     2^15 goes multi-pass (segments of 2^3)."""
     rng = np.random.default_rng(3)
@@ -148,10 +148,11 @@ def test_two_pass_library_size(emu):
 @pytest.mark.parametrize("logn", range(1, 15))
 def test_specialised_tile_as_launched(emu, logn):
     """The compile-time specialised tile kernel with the GPU's own tile size
-    and thread count (2^12-cell tiles of 256 threads up to N = 2^12, then
-    512 and 1024 threads), on a full tile and on a ragged last tile."""
+    and thread count (2^10-cell tiles of 64 threads up to N = 2^10, then one
+    transform per tile with 128 .. 1024 threads), on a full tile and on a
+    ragged last tile."""
     N = 1 << logn
-    T = max(1, 4096 // N) if logn <= 12 else 1
+    T = max(1, 1024 // N)  # transforms per tile: 2^max(10, logn) cells
     for Tact in sorted({T, max(1, T // 2 - 1)}):
         x = workloads.uniform(700 + logn + Tact, (Tact, N))
         xf = _as_c64(x)
@@ -184,7 +185,7 @@ def test_specialised_tile_offset_list(emu, logn, swap):
     transform t read from and written to element offset offs[t] (here a
     scrambled order with gaps that other transforms' data fill)."""
     N = 1 << logn
-    T = max(1, 4096 // N) if logn <= 12 else 1
+    T = max(1, 1024 // N)  # transforms per tile: 2^max(10, logn) cells
     Tact = max(1, T - 1)
     rng = np.random.default_rng(logn)
     slots = rng.permutation(Tact + 2)[:Tact]  # transforms at scattered slots
@@ -215,7 +216,7 @@ def test_specialised_tile_real_input(emu, logn, odd):
     against the oracle's rdft; an odd number of signals leaves the last
     slot's second lane empty."""
     N = 1 << logn
-    T = max(1, 4096 // N) if logn <= 12 else 1
+    T = max(1, 1024 // N)  # transforms per tile: 2^max(10, logn) cells
     rows = min(2 * T, 6) - odd
     x = np.ascontiguousarray(workloads.normal(1200 + logn, (rows, N)).real.astype(np.float32))
     out = np.full((rows, N // 2 + 1), np.nan + 1j * np.nan, dtype=np.complex64)
@@ -240,7 +241,7 @@ def test_specialised_tile_dct0_dst0(emu, logn, which):
     h = N // 2
     if which == "dst" and h - 1 == 0:
         pytest.skip("the DST-0 of N = 2 is empty")
-    T = max(1, 4096 // N) if logn <= 12 else 1
+    T = max(1, 1024 // N)  # transforms per tile: 2^max(10, logn) cells
     rows = min(5, 2 * T)
     c = np.ascontiguousarray(workloads.uniform(1300 + logn, (rows, h + 1)).real.astype(np.float32))
     d = np.ascontiguousarray(workloads.uniform(1400 + logn, (rows, max(h - 1, 1))).real

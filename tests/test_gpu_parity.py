@@ -347,7 +347,9 @@ def test_uneven_schedules_and_autotune():
     plan = qft.UnevenPlan(r.tolist())
     names = plan.schedules
     say(f"uneven schedules {names}")
-    assert names[0] == "t14:6-14" and len(names) == 8
+    # 7 tile-size assignments (2^10 .. 2^14 tiles), each persistent and "/all"
+    assert names[0] == "t14:6-14" and len(names) == 14
+    assert "t10:6-10+t11:11+t12:12+t13:13+t14:14" in names
     fw, bw = [], []
     for i in range(len(names)):
         plan.schedule = i
