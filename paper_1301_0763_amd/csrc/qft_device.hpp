@@ -1736,19 +1736,6 @@ QFT_HD void chain_one_side(SP sd, SP top, int plog, int tid, int nthr, int wave_
   }
 }
 
-// Value of heap cell p (p >= 1) of one side of an N-point transform straight
-// from x: the folded sample c(n) = x(n) + x(N-n) (DCT) or d(n) = x(n) - x(N-n)
-// (DST) with n = (N / 4M)(2v+1) for the block M = 2^floor(log2 p), v = p - M.
-template <int DT, bool SWAP, bool DST>
-QFT_HD float2 heap_fold_value(const typename Store<DT>::T* xt, int logn, int p) {
-  const int lgM = 31 - __builtin_clz(p);
-  const int v = p - (1 << lgM);
-  const int n = (2 * v + 1) << (logn - 2 - lgM);
-  const float2 a = sw<SWAP>(Store<DT>::ld(xt, n));
-  const float2 b = sw<SWAP>(Store<DT>::ld(xt, (1 << logn) - n));
-  return DST ? csub(a, b) : cadd(a, b);
-}
-
 // Pass B, thread k of a transform (0 <= k < N/8).  Heap contents after pass A
 // (DCT side; the DST side is alike with its own index conventions):
 //   cells [0, MC) + top : D_{N/4} (chain output of the head)
@@ -1827,8 +1814,9 @@ struct HeadSides {  // the head segments of pass A: DCT, DST and the top cell
 };
 
 // Folded heap values of position q of segment j < 2 (both sides) straight
-// from x: c(n) = x(n) + x(N-n), d(n) = x(n) - x(N-n) with the n of heap cell
-// p = j MC + q (heap_fold_value); cell 0 holds c(0) (its DST cell is unused).
+// from x: c(n) = x(n) + x(N-n), d(n) = x(n) - x(N-n) with n = (N/4M)(2v+1)
+// for heap cell p = j MC + q in block M = 2^floor(log2 p), v = p - M; cell
+// 0 holds c(0) (its DST cell is unused).
 template <int DT, bool SWAP, int MC_LOG2>
 QFT_HD void tp_gather01(const typename Store<DT>::T* xt, int j, int q, float2& vc, float2& vs) {
   constexpr int MC = 1 << MC_LOG2;
