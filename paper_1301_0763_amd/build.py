@@ -8,7 +8,7 @@ storage type (``-DQFT_MP_DT=0`` complex FP32, ``=1`` complex FP16) and
 (``-DQFT_TILE_TL=10 .. 14``) and direction (``-DQFT_TILE_SWAP=0`` forward,
 ``=1`` adjoint).
 
-Flags: ``--offload-arch=gfx950 -O3`` and packed FP32 instructions disabled
+Flags: ``--offload-arch=gfx950 -O3 -ffp-contract=off`` and packed FP32 instructions disabled
 (``-Xclang -target-feature -Xclang -packed-fp32-ops``; the host pass warns
 that it does not know the feature, which is harmless).
 """
@@ -28,8 +28,12 @@ LIB = os.path.join(HERE, "libqft.so")
 ROOT = os.path.dirname(HERE)
 HEADER = os.path.join(ROOT, "include", "qft.h")
 
+# -ffp-contract=off: every kernel rounds each product and sum as written,
+# so the same transform gives bit-identical results in every kernel that
+# computes it (uniform, uneven and real-input tiles, any schedule), whatever
+# the surrounding code lets the optimiser fuse.
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 NOISE = "is not a recognized feature for this target"

@@ -580,6 +580,42 @@ QFT_HD void mp_bwd_group_item(RP Win, WP Wout, int logn, int s, int64_t i) {
 // ===========================================================================
 template <int A, int B> struct cmin { static constexpr int v = A < B ? A : B; };
 
+// Thread -> item map of one LDS pass over NS sides of 2^LGS cells, in items
+// of 2^LGE consecutive (tail, backward) or segment-spanning (forward) cells,
+// for NT threads in waves of WAVE lanes.  Where every thread gets the same
+// number of items, wave w takes items [w I, (w+1) I), I = items per wave, in
+// lane-consecutive order: it then touches only the cells [w C, (w+1) C) of
+// the buffer (C = cells per wave) whenever the pass's segments (2^LGSEG
+// cells) are no longer than C.  Two such passes in a row need no workgroup
+// barrier between them, only the wave's own ordering.
+template <int NS, int LGS, int NT, int WAVE, int LGE, int LGSEG>
+struct PassMap {
+  static constexpr int total = NS << (LGS - LGE);
+  static constexpr int NI = (total + NT - 1) / NT;
+  static constexpr int WE = NT < WAVE ? NT : WAVE;
+  static constexpr int NW = NT / WE;
+  static_assert(NW == 1 || NT % WAVE == 0, "whole waves");
+  static constexpr bool blocked = NW > 1 && total == NI * NT;
+  static constexpr int C = blocked ? NI * WE << LGE : 0;
+  static constexpr bool local = NW == 1 || (blocked && (1 << LGSEG) <= C);
+  static QFT_HD int item(int tid, int it) {
+    if constexpr (blocked) {
+      const int w = tid / WE;
+      return w * (NI * WE) + it * WE + (tid - w * WE);
+    } else {
+      return tid + it * NT;
+    }
+  }
+};
+
+// The ordering between two LDS passes: the wave's own where both stay in
+// the wave's cells, else a workgroup barrier.
+template <bool WAVE_ONLY, class Sync, class WSync>
+QFT_HD void pass_sync(Sync sync, WSync wsync) {
+  if constexpr (WAVE_ONLY) wsync();
+  else sync();
+}
+
 template <int K, int S, bool DST, typename SP>
 QFT_HD void fwd_group_s(SP sd, int j, int x, const float* __restrict__ sec, bool skip0) {
   constexpr int G = S >> K;
@@ -638,15 +674,16 @@ QFT_HD void fwd_group_s(SP sd, int j, int x, const float* __restrict__ sec, bool
   }
 }
 
-template <int K, int HI, int LGS, int NS, int NT, int MODE, bool SKIP0, typename WP>
+template <int K, int HI, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0, typename WP>
 QFT_HD void fwd_chunk_s(WP W, const float* sec, int tid) {
+  using Map = PassMap<NS, LGS, NT, WAVE, K + 1, HI>;
   constexpr int lgGroups = LGS - K - 1;
-  constexpr int total = NS << lgGroups;
-  constexpr int NI = (total + NT - 1) / NT;
+  constexpr int total = Map::total;
+  constexpr int NI = Map::NI;
   constexpr int lgHalfG = HI - K - 1;
 #pragma unroll
   for (int it = 0; it < NI; ++it) {
-    const int i = tid + it * NT;
+    const int i = Map::item(tid, it);
     if ((total % NT) != 0 && i >= total) break;
     const int s = i >> lgGroups;
     const int g = i & ((1 << lgGroups) - 1);
@@ -660,14 +697,15 @@ QFT_HD void fwd_chunk_s(WP W, const float* sec, int tid) {
   }
 }
 
-template <int K, int LGS, int NS, int NT, int MODE, bool SKIP0, typename WP>
+template <int K, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0, typename WP>
 QFT_HD void tail_chunk_s(WP W, const float* sec, int tid) {
+  using Map = PassMap<NS, LGS, NT, WAVE, K, K>;
   constexpr int lgGroups = LGS - K;
-  constexpr int total = NS << lgGroups;
-  constexpr int NI = (total + NT - 1) / NT;
+  constexpr int total = Map::total;
+  constexpr int NI = Map::NI;
 #pragma unroll
   for (int it = 0; it < NI; ++it) {
-    const int i = tid + it * NT;
+    const int i = Map::item(tid, it);
     if ((total % NT) != 0 && i >= total) break;
     const int s = i >> lgGroups;
     const int g = i & ((1 << lgGroups) - 1);
@@ -679,22 +717,26 @@ QFT_HD void tail_chunk_s(WP W, const float* sec, int tid) {
   }
 }
 
-template <int K, int LO, int LGS, int NS, int NT, int MODE, bool SKIP0, class Sync, typename WP>
-QFT_HD void bwd_chunk_s(WP W, int tid, Sync sync) {
+// Ends with the ordering before the next pass: the wave's own if NEXT_LOCAL
+// and this pass stays in the wave's cells, else a workgroup barrier.
+template <int K, int LO, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0, bool NEXT_LOCAL,
+          class Sync, class WSync, typename WP>
+QFT_HD void bwd_chunk_s(WP W, int tid, Sync sync, WSync wsync) {
+  using Map = PassMap<NS, LGS, NT, WAVE, K, LO + K - 1>;
   constexpr int R = 1 << K;
   constexpr int S = 1 << (LO + K - 1);
   constexpr int lgG = LO - 1;
   constexpr int G = 1 << lgG;
   constexpr int lgGroups = LGS - K;
-  constexpr int total = NS << lgGroups;
-  constexpr int NI = (total + NT - 1) / NT;
+  constexpr int total = Map::total;
+  constexpr int NI = Map::NI;
   // the R <= 8 outputs of an item are a run inside one padding block (sides
   // start on a block boundary)
   static_assert(K <= 3, "runs of at most 8 cells");
   float2 y[NI][R];
 #pragma unroll
   for (int it = 0; it < NI; ++it) {
-    const int i = tid + it * NT;
+    const int i = Map::item(tid, it);
     if ((total % NT) != 0 && i >= total) break;
     const int s = i >> lgGroups;
     const int g = i & ((1 << lgGroups) - 1);
@@ -709,10 +751,10 @@ QFT_HD void bwd_chunk_s(WP W, int tid, Sync sync) {
       else bwd_group_load_s<K, G, false>(sd, j * S, ii, y[it]);
     }
   }
-  sync();
+  pass_sync<Map::local>(sync, wsync);
 #pragma unroll
   for (int it = 0; it < NI; ++it) {
-    const int i = tid + it * NT;
+    const int i = Map::item(tid, it);
     if ((total % NT) != 0 && i >= total) break;
     const int s = i >> lgGroups;
     const int g = i & ((1 << lgGroups) - 1);
@@ -726,7 +768,7 @@ QFT_HD void bwd_chunk_s(WP W, int tid, Sync sync) {
       for (int e = 0; e < R; ++e) r.run(e) = y[it][e];
     }
   }
-  sync();
+  pass_sync<Map::local && NEXT_LOCAL>(sync, wsync);
 }
 
 // Rounds per LDS pass (KC) of the forward and backward chunks, and fused
@@ -737,36 +779,71 @@ QFT_HD constexpr int sweep_tail_rounds(int top) {
   return top < 4 ? top : ((top - 4) % QFT_KC == 0 ? 4 : 3);
 }
 
-// forward chunks for rounds (KT, HI], top down
-template <int HI, int KT, int LGS, int NS, int NT, int MODE, bool SKIP0, class Sync, typename WP>
-QFT_HD void fwd_rounds_s(WP W, const float* sec, int tid, Sync sync) {
+// Whether the LDS pass that follows the forward chunk ending at round 2^HI
+// (the next forward chunk, else the tail of KT rounds) stays in each wave's
+// cells (PassMap).
+template <int HI, int KT, int LGS, int NS, int NT, int WAVE>
+QFT_HD constexpr bool fwd_next_local() {
   if constexpr (HI > KT) {
     constexpr int K = cmin<QFT_KC, HI - KT>::v;
-    fwd_chunk_s<K, HI, LGS, NS, NT, MODE, SKIP0>(W, sec, tid);
-    sync();
-    fwd_rounds_s<HI - K, KT, LGS, NS, NT, MODE, SKIP0>(W, sec, tid, sync);
+    return PassMap<NS, LGS, NT, WAVE, K + 1, HI>::local;
+  } else {
+    return PassMap<NS, LGS, NT, WAVE, KT, KT>::local;
   }
 }
 
-// backward chunks for rounds [LO, TOP], bottom up
-template <int LO, int TOP, int LGS, int NS, int NT, int MODE, bool SKIP0, class Sync, typename WP>
-QFT_HD void bwd_rounds_s(WP W, int tid, Sync sync) {
+// forward chunks for rounds (KT, HI], top down, each followed by the
+// ordering the next pass needs
+template <int HI, int KT, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0, class Sync,
+          class WSync, typename WP>
+QFT_HD void fwd_rounds_s(WP W, const float* sec, int tid, Sync sync, WSync wsync) {
+  if constexpr (HI > KT) {
+    constexpr int K = cmin<QFT_KC, HI - KT>::v;
+    fwd_chunk_s<K, HI, LGS, NS, NT, WAVE, MODE, SKIP0>(W, sec, tid);
+    pass_sync<PassMap<NS, LGS, NT, WAVE, K + 1, HI>::local &&
+              fwd_next_local<HI - K, KT, LGS, NS, NT, WAVE>()>(sync, wsync);
+    fwd_rounds_s<HI - K, KT, LGS, NS, NT, WAVE, MODE, SKIP0>(W, sec, tid, sync, wsync);
+  }
+}
+
+// Whether the backward chunk starting at round 2^LO (if LO <= TOP) stays in
+// each wave's cells; past the last chunk the caller's next stage does not.
+template <int LO, int TOP, int LGS, int NS, int NT, int WAVE>
+QFT_HD constexpr bool bwd_local() {
   if constexpr (LO <= TOP) {
     constexpr int K = cmin<QFT_KC, TOP - LO + 1>::v;
-    bwd_chunk_s<K, LO, LGS, NS, NT, MODE, SKIP0>(W, tid, sync);
-    bwd_rounds_s<LO + K, TOP, LGS, NS, NT, MODE, SKIP0>(W, tid, sync);
+    return PassMap<NS, LGS, NT, WAVE, K, LO + K - 1>::local;
+  } else {
+    return false;
+  }
+}
+
+// backward chunks for rounds [LO, TOP], bottom up; the last one ends with a
+// workgroup barrier
+template <int LO, int TOP, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0, class Sync,
+          class WSync, typename WP>
+QFT_HD void bwd_rounds_s(WP W, int tid, Sync sync, WSync wsync) {
+  if constexpr (LO <= TOP) {
+    constexpr int K = cmin<QFT_KC, TOP - LO + 1>::v;
+    bwd_chunk_s<K, LO, LGS, NS, NT, WAVE, MODE, SKIP0,
+                bwd_local<LO + K, TOP, LGS, NS, NT, WAVE>()>(W, tid, sync, wsync);
+    bwd_rounds_s<LO + K, TOP, LGS, NS, NT, WAVE, MODE, SKIP0>(W, tid, sync, wsync);
   }
 }
 
 // Forward rounds S = 2^TOP .. 2 and backward rounds back up (TOP >= 1).
-template <int TOP, int LGS, int NS, int NT, int MODE, bool SKIP0, class Sync, typename WP>
-QFT_HD void sweeps_s(WP W, const float* sec, int tid, Sync sync) {
+// Expects a workgroup barrier before and ends with one; in between, passes
+// whose segments fit one wave's cells are ordered by the wave alone.
+template <int TOP, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0, class Sync,
+          class WSync, typename WP>
+QFT_HD void sweeps_s(WP W, const float* sec, int tid, Sync sync, WSync wsync) {
   if constexpr (TOP >= 1) {
     constexpr int KT = sweep_tail_rounds(TOP);
-    fwd_rounds_s<TOP, KT, LGS, NS, NT, MODE, SKIP0>(W, sec, tid, sync);
-    tail_chunk_s<KT, LGS, NS, NT, MODE, SKIP0>(W, sec, tid);
-    sync();
-    bwd_rounds_s<KT + 1, TOP, LGS, NS, NT, MODE, SKIP0>(W, tid, sync);
+    fwd_rounds_s<TOP, KT, LGS, NS, NT, WAVE, MODE, SKIP0>(W, sec, tid, sync, wsync);
+    tail_chunk_s<KT, LGS, NS, NT, WAVE, MODE, SKIP0>(W, sec, tid);
+    pass_sync<PassMap<NS, LGS, NT, WAVE, KT, KT>::local &&
+              bwd_local<KT + 1, TOP, LGS, NS, NT, WAVE>()>(sync, wsync);
+    bwd_rounds_s<KT + 1, TOP, LGS, NS, NT, WAVE, MODE, SKIP0>(W, tid, sync, wsync);
   }
 }
 
@@ -1660,7 +1737,7 @@ QFT_HD void tile_body_s(const IO& io, WP W, int Tact, const float* sec, int tid,
   }
   sync();
   if constexpr (LOGN >= 3)
-    sweeps_s<LOGN - 2, LOGN - 1, 2 * T, NT, SIDES_ALT, true>(W, sec, tid, sync);
+    sweeps_s<LOGN - 2, LOGN - 1, 2 * T, NT, WAVE, SIDES_ALT, true>(W, sec, tid, sync, wsync);
   if constexpr (LOGN >= 5) {
     chain_fused<LOGN, T, NT, WAVE, true>(TileSides<WP>{W, LOGN}, io, Tact, tid, sync, wsync);
     return;
@@ -1872,7 +1949,7 @@ QFT_HD void tp_segment(GP wt, LP L, int j, int h, const float* sec, int tid, Syn
   constexpr int NI = MC / NT;
   sync();
   if (j == 0) {
-    sweeps_s<MC_LOG2 - 1, MC_LOG2, 2, NT, SIDES_ALT, true>(L, sec, tid, sync);
+    sweeps_s<MC_LOG2 - 1, MC_LOG2, 2, NT, WAVE, SIDES_ALT, true>(L, sec, tid, sync, wsync);
     if constexpr (MC_LOG2 + 1 >= 5) {
       chain_fused<MC_LOG2 + 1, 1, NT, WAVE, false>(HeadSides<LP>{L, MC}, NoIO{}, 1, tid, sync,
                                                     wsync);
@@ -1881,7 +1958,7 @@ QFT_HD void tp_segment(GP wt, LP L, int j, int h, const float* sec, int tid, Syn
       chain_one_side<true>(L + MC, L + 2 * MC, MC_LOG2 + 1, tid, NT, WAVE, sync, wsync);
     }
   } else {
-    sweeps_s<MC_LOG2, MC_LOG2, 2, NT, SIDES_ALT, false>(L, sec, tid, sync);
+    sweeps_s<MC_LOG2, MC_LOG2, 2, NT, WAVE, SIDES_ALT, false>(L, sec, tid, sync, wsync);
   }
 #pragma unroll
   for (int it = 0; it < NI; ++it) {

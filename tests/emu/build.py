@@ -37,8 +37,9 @@ def load():
     L.emu_tile_s.argtypes = [i, i, vp, vp, i, i, vp]
     L.emu_tile_real.argtypes = [i, i, i, i64, vp, vp, vp, vp]
     L.emu_multipass_real.argtypes = [i, i, i, i64, vp, vp, vp, vp, i, i]
+    L.emu_race_model_check.argtypes = [i, i]
     for f in (L.emu_multipass, L.emu_uneven, L.emu_twopass, L.emu_tile_s,
-              L.emu_tile_real, L.emu_multipass_real):
+              L.emu_tile_real, L.emu_multipass_real, L.emu_race_model_check):
         f.restype = i
     return L
 

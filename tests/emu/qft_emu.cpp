@@ -6,7 +6,9 @@
 //  * every LDS (and heap-buffer) access goes through a tracking pointer; at
 //    each barrier (and at the end of every emulated global pass) a cell that
 //    was written by one thread and touched by another within the same phase
-//    is counted as a race.
+//    is counted as a race, unless both threads are lanes of one wavefront
+//    (64 consecutive threads) and a wave-level sync of that wavefront lies
+//    between the two accesses (its lanes are then ordered, as on the GPU).
 // Entry points return the number of races found (>= 0) or a negative error.
 #include <hip/hip_runtime.h>
 
@@ -15,6 +17,8 @@
 #include <cstdint>
 #include <cstring>
 #include <functional>
+#include <memory>
+#include <algorithm>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -26,6 +30,8 @@ namespace {
 
 struct Entry {
   int64_t cell;
+  int64_t wave;  // wavefront of the actor (a unique id per workgroup wave)
+  int64_t wp;    // wave-level syncs that wavefront had passed
   int64_t actor;
   bool write;
 };
@@ -35,43 +41,72 @@ struct Tracker {
   int64_t races = 0;
   std::atomic<int64_t> oob{0};  // accesses outside the tracked buffer
   explicit Tracker(int slots) : logs(slots) {}
+  // A cell races if two different actors touched it and one of them wrote,
+  // unless both belong to one wavefront and touched it in different wave
+  // phases.
   void end_phase() {
-    struct St {
-      int64_t actor;
-      bool multi;
-      bool written;
-    };
-    std::unordered_map<int64_t, St> m;
+    std::vector<Entry> all;
+    size_t n = 0;
+    for (auto& lg : logs) n += lg.size();
+    all.reserve(n);
     for (auto& lg : logs) {
-      for (const Entry& e : lg) {
-        auto it = m.find(e.cell);
-        if (it == m.end()) {
-          m.emplace(e.cell, St{e.actor, false, e.write});
-        } else {
-          if (it->second.actor != e.actor) it->second.multi = true;
-          it->second.written |= e.write;
-        }
-      }
+      all.insert(all.end(), lg.begin(), lg.end());
       lg.clear();
     }
-    for (auto& kv : m)
-      if (kv.second.multi && kv.second.written) ++races;
+    std::sort(all.begin(), all.end(), [](const Entry& a, const Entry& b) {
+      if (a.cell != b.cell) return a.cell < b.cell;
+      if (a.wave != b.wave) return a.wave < b.wave;
+      return a.wp < b.wp;
+    });
+    for (size_t i = 0; i < all.size();) {
+      size_t e = i;
+      bool written = false, multi_wave = false;
+      while (e < all.size() && all[e].cell == all[i].cell) {
+        written |= all[e].write;
+        multi_wave |= all[e].wave != all[i].wave;
+        ++e;
+      }
+      bool race = written && multi_wave;
+      for (size_t a = i; !race && a < e;) {  // one wave: phase by phase
+        size_t b = a;
+        bool w = false, multi_actor = false;
+        while (b < e && all[b].wp == all[a].wp) {
+          w |= all[b].write;
+          multi_actor |= all[b].actor != all[a].actor;
+          ++b;
+        }
+        race = w && multi_actor;
+        a = b;
+      }
+      races += race;
+      i = e;
+    }
   }
 };
 
 thread_local int tl_slot = 0;       // which log this OS thread appends to
 thread_local int64_t tl_actor = 0;  // emulated GPU thread / work item
+thread_local int64_t tl_wave = 0;   // its wavefront
+thread_local int64_t tl_wp = 0;     // wave-level syncs passed by that wavefront
+std::atomic<int64_t> g_workgroups{0};
+
+// A work item of a global pass: its own wavefront (no wave-level syncs).
+inline void set_item_actor(int64_t a) {
+  tl_actor = a;
+  tl_wave = -1 - a;
+  tl_wp = 0;
+}
 
 struct Ref {
   float2* p;
   int64_t cell;
   Tracker* tr;
   operator float2() const {
-    tr->logs[tl_slot].push_back({cell, tl_actor, false});
+    tr->logs[tl_slot].push_back({cell, tl_wave, tl_wp, tl_actor, false});
     return *p;
   }
   Ref& operator=(float2 v) {
-    tr->logs[tl_slot].push_back({cell, tl_actor, true});
+    tr->logs[tl_slot].push_back({cell, tl_wave, tl_wp, tl_actor, true});
     *p = v;
     return *this;
   }
@@ -128,22 +163,38 @@ inline TRow pad_row(const TPtr& sd, int a) {
 
 constexpr int kEmuPad = 4;  // same LDS padding as the GPU kernels
 
-// Runs fn(tid, sync) on nthr threads sharing one barrier whose completion
-// closes a tracker phase.
+// Runs fn(tid, sync, wsync) on nthr threads sharing one barrier whose
+// completion closes a tracker phase; wsync is a barrier of the thread's
+// wavefront (threads 64 w .. 64 w + 63) that starts a new wave phase.
 template <class F>
 void run_workgroup(int nthr, Tracker& tr, F fn) {
+  constexpr int kLanes = 64;
   auto done = [&tr]() noexcept { tr.end_phase(); };
   std::barrier bar(nthr, done);
+  const int nw = (nthr + kLanes - 1) / kLanes;
+  std::vector<std::unique_ptr<std::barrier<>>> wbar;
+  for (int w = 0; w < nw; ++w)
+    wbar.emplace_back(new std::barrier<>(std::min(kLanes, nthr - w * kLanes)));
+  const int64_t wg = g_workgroups++;
   struct HostSync {
     decltype(bar)* b;
     void operator()() const { b->arrive_and_wait(); }
+  };
+  struct HostWaveSync {
+    std::barrier<>* b;
+    void operator()() const {
+      b->arrive_and_wait();
+      ++tl_wp;
+    }
   };
   std::vector<std::thread> th;
   for (int t = 0; t < nthr; ++t) {
     th.emplace_back([&, t]() {
       tl_slot = t;
       tl_actor = t;
-      fn(t, HostSync{&bar});
+      tl_wave = wg * 1024 + t / kLanes;
+      tl_wp = 0;
+      fn(t, HostSync{&bar}, HostWaveSync{wbar[t / kLanes].get()});
     });
   }
   for (auto& x : th) x.join();
@@ -165,13 +216,13 @@ int tile_s_impl(const void* x, void* X, int Tact, const float* sec, const int64_
   std::vector<float2> lds(cells + (cells >> kEmuPad));
   Tracker tr(NT);
   TPtr W{lds.data(), 0, &tr, cells, kEmuPad};
-  run_workgroup(NT, tr, [&](int tid, auto sync) {
+  run_workgroup(NT, tr, [&](int tid, auto sync, auto wsync) {
     if (offs) {
       const qftk::GatherIO<DT, SWAP> io((const E*)x, (E*)X, offs, LOGN);
-      qftk::tile_body_s<LOGN, T, NT, 64>(io, W, Tact, sec, tid, sync, sync);
+      qftk::tile_body_s<LOGN, T, NT, 64>(io, W, Tact, sec, tid, sync, wsync);
     } else {
       const qftk::ContigIO<DT, SWAP, LOGN> io((const E*)x, (E*)X);
-      qftk::tile_body_s<LOGN, T, NT, 64>(io, W, Tact, sec, tid, sync, sync);
+      qftk::tile_body_s<LOGN, T, NT, 64>(io, W, Tact, sec, tid, sync, wsync);
     }
   });
   return tr.oob ? -100 : (int)tr.races;
@@ -193,13 +244,13 @@ int tile_real_impl(int64_t rows, const void* in0, const void* in1, void* out0, v
   std::vector<float2> lds(cells + (cells >> kEmuPad));
   Tracker tr(NT);
   TPtr W{lds.data(), 0, &tr, cells, kEmuPad};
-  run_workgroup(NT, tr, [&](int tid, auto sync) {
+  run_workgroup(NT, tr, [&](int tid, auto sync, auto wsync) {
     if constexpr (KIND == 0) {
       const qftk::RealPairIO<DT, LOGN> io{(const R*)in0, (E*)out0, rows};
-      qftk::tile_body_s<LOGN, T, NT, 64>(io, W, slots, sec, tid, sync, sync);
+      qftk::tile_body_s<LOGN, T, NT, 64>(io, W, slots, sec, tid, sync, wsync);
     } else {
       const qftk::DctDstIO<DT, LOGN> io{(const R*)in0, (const R*)in1, (R*)out0, (R*)out1, rows};
-      qftk::tile_body_s<LOGN, T, NT, 64>(io, W, slots, sec, tid, sync, sync);
+      qftk::tile_body_s<LOGN, T, NT, 64>(io, W, slots, sec, tid, sync, wsync);
     }
   });
   return tr.oob ? -100 : (int)tr.races;
@@ -267,7 +318,7 @@ struct EmuMultipass {
   void items(int64_t total, F f) {
     tl_slot = 0;
     for (int64_t i = 0; i < total; ++i) {
-      tl_actor = i;
+      set_item_actor(i);
       f(i);
     }
     gtr.end_phase();
@@ -305,8 +356,8 @@ struct EmuMultipass {
       Tracker ltr(NT);
       TPtr L{lds.data(), 0, &ltr, lc, kEmuPad};
       float2* wt = cur + (t << logn);
-      run_workgroup(NT, ltr, [&](int tid, auto sync) {
-        qftk::mp_segment_pair<MC_LOG2, NT, 64>(wt, L, 1 << (logn - 1), j, sec, tid, sync, sync);
+      run_workgroup(NT, ltr, [&](int tid, auto sync, auto wsync) {
+        qftk::mp_segment_pair<MC_LOG2, NT, 64>(wt, L, 1 << (logn - 1), j, sec, tid, sync, wsync);
       });
       races += ltr.races;
       if (ltr.oob) races = -1000000;
@@ -468,10 +519,10 @@ int twopass_mc(const void* x, void* X, int64_t batch) {
       Tracker ltr(NT);
       TPtr L{lds.data(), 0, &ltr, lc, kEmuPad};
       const E* xt = (const E*)x + (t << logn);
-      run_workgroup(NT, ltr, [&](int tid, auto sync) {
+      run_workgroup(NT, ltr, [&](int tid, auto sync, auto wsync) {
         tl_actor = (t * 4 + j) * NT + tid;  // unique over all workgroups
         qftk::tp_pass_a2<DT, SWAP, MC_LOG2, NT, 64>(xt, A + (t << logn), L, j, sec.data(), tid,
-                                                    sync, sync);
+                                                    sync, wsync);
       });
       if (ltr.oob) return -102;
       races += ltr.races;
@@ -486,7 +537,7 @@ int twopass_mc(const void* x, void* X, int64_t batch) {
   tl_slot = 0;
   for (int64_t t = 0; t < batch; ++t) {
     for (int k = 0; k < (1 << (logn - 3)); ++k) {
-      tl_actor = t * 100000 + k;
+      set_item_actor(t * 100000 + k);
       qftk::tp_pass_b<DT, SWAP, MC_LOG2>(G + (t << logn), (E*)X + (t << logn), k);
     }
   }
@@ -575,6 +626,27 @@ int emu_uneven(int dt, int swap, const void* x, void* X, const int32_t* log2n, i
                            : uneven_impl<0, false>(x, X, log2n, count, seg_log2, nthr);
   return swap ? uneven_impl<1, true>(x, X, log2n, count, seg_log2, nthr)
               : uneven_impl<1, false>(x, X, log2n, count, seg_log2, nthr);
+}
+
+// Checks the race model on a 128-thread workgroup (two wavefronts) over a
+// 128-cell buffer: every thread writes cell tid, then, after `order` (0:
+// nothing, 1: a wave-level sync, 2: a workgroup barrier), reads cell
+// partner(tid) = tid ^ 1 (its own wavefront) for same_wave != 0, else
+// (tid + 64) % 128 (the other wavefront).  Returns the races found.
+int emu_race_model_check(int order, int same_wave) {
+  constexpr int nthr = 128;
+  std::vector<float2> buf(nthr);
+  Tracker tr(nthr);
+  TPtr B{buf.data(), 0, &tr, nthr};
+  run_workgroup(nthr, tr, [&](int tid, auto sync, auto wsync) {
+    B[tid] = make_float2((float)tid, 0.f);
+    if (order == 1) wsync();
+    if (order == 2) sync();
+    const int p = same_wave ? (tid ^ 1) : (tid + 64) % nthr;
+    const float2 v = B[p];
+    (void)v;
+  });
+  return (int)tr.races;
 }
 
 }  // extern "C"

@@ -32,6 +32,22 @@ def _as_c64(x):
     return np.ascontiguousarray(x.astype(np.complex64))
 
 
+@pytest.mark.parametrize("order,same_wave,expect_race", [
+    (0, 1, True),   # no ordering at all
+    (0, 0, True),
+    (1, 1, False),  # a wave-level sync orders the lanes of one wavefront
+    (1, 0, True),   # ... but not two wavefronts
+    (2, 1, False),  # a workgroup barrier orders everything
+    (2, 0, False),
+])
+def test_race_model(emu, order, same_wave, expect_race):
+    """The emulator's race tracker: a write and a read of one cell by two
+    threads race unless a workgroup barrier lies between them, or a
+    wave-level sync and both threads are lanes of one wavefront."""
+    races = emu.emu_race_model_check(order, same_wave)
+    assert (races > 0) == expect_race, races
+
+
 def _tol(logn):
     return 1e-5 * logn
 
