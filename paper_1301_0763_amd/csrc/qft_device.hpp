@@ -1894,24 +1894,23 @@ struct HeadSides {  // the head segments of pass A: DCT, DST and the top cell
 // from x: c(n) = x(n) + x(N-n), d(n) = x(n) - x(N-n) with n = (N/4M)(2v+1)
 // for heap cell p = j MC + q in block M = 2^floor(log2 p), v = p - M; cell
 // 0 holds c(0) (its DST cell is unused).
+// Branch-free, so that the loads of all of a thread's positions are in
+// flight together: cell 0 loads x(0) and, unused, x(3N/4).
 template <int DT, bool SWAP, int MC_LOG2>
 QFT_HD void tp_gather01(const typename Store<DT>::T* xt, int j, int q, float2& vc, float2& vs) {
   constexpr int MC = 1 << MC_LOG2;
   constexpr int logn = MC_LOG2 + 3;
   constexpr int N = 1 << logn;
   const int p = j * MC + q;
-  if (p == 0) {
-    vc = sw<SWAP>(Store<DT>::ld(xt, 0));  // c(0)
-    vs = make_float2(0.f, 0.f);
-  } else {
-    const int lgM = 31 - __builtin_clz(p);
-    const int v = p - (1 << lgM);
-    const int n = (2 * v + 1) << (logn - 2 - lgM);
-    const float2 a = sw<SWAP>(Store<DT>::ld(xt, n));
-    const float2 b = sw<SWAP>(Store<DT>::ld(xt, N - n));
-    vc = cadd(a, b);
-    vs = csub(a, b);
-  }
+  const bool zero = p == 0;
+  const int pp = zero ? 1 : p;
+  const int lgM = 31 - __builtin_clz(pp);
+  const int v = pp - (1 << lgM);
+  const int n = (2 * v + 1) << (logn - 2 - lgM);
+  const float2 a = sw<SWAP>(Store<DT>::ld(xt, zero ? 0 : n));
+  const float2 b = sw<SWAP>(Store<DT>::ld(xt, N - n));
+  vc = zero ? a : cadd(a, b);                       // c(0) for cell 0
+  vs = zero ? make_float2(0.f, 0.f) : csub(a, b);
 }
 
 // Segments 2 and 3 (the halves of the block N/4 after its top forward round,
@@ -1980,14 +1979,16 @@ QFT_HD void tp_pass_a2(const typename Store<DT>::T* xt, GP wt, LP L, int j, cons
   constexpr int h = 4 * MC;
   constexpr int NI = MC / NT;  // positions per thread
   float2 vc[NI], vs[NI];
+  // j is uniform over the workgroup: one branch around straight-line loads
+  if (j < 2) {
 #pragma unroll
-  for (int it = 0; it < NI; ++it) {
-    const int q = tid + it * NT;
-    if (j < 2) {
-      tp_gather01<DT, SWAP, MC_LOG2>(xt, j, q, vc[it], vs[it]);
-    } else {
+    for (int it = 0; it < NI; ++it)
+      tp_gather01<DT, SWAP, MC_LOG2>(xt, j, tid + it * NT, vc[it], vs[it]);
+  } else {
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
       float2 c2, s2, c3, s3;
-      tp_gather23<DT, SWAP, MC_LOG2>(xt, q, sec, c2, s2, c3, s3);
+      tp_gather23<DT, SWAP, MC_LOG2>(xt, tid + it * NT, sec, c2, s2, c3, s3);
       vc[it] = j == 2 ? c2 : c3;
       vs[it] = j == 2 ? s2 : s3;
     }
