@@ -571,6 +571,58 @@ QFT_HD void mp_bwd_group_item(RP Win, WP Wout, int logn, int s, int64_t i) {
 
 
 
+// The same backward rounds for the items of one wavefront of LANES lanes
+// (lane = i mod LANES).  An item of a segment j >= 1 computes 2^K
+// consecutive outputs, so storing them straight from each lane would spread
+// every store instruction over LANES runs.  A segment holds 2^(hi-K) >=
+// LANES items, so the wave's items belong to one segment of one side and
+// their outputs are LANES * 2^K consecutive cells: the wave passes them
+// through its LDS rows ws (LANES * ROW cells) in chunks of CH outputs per
+// lane (a 128-byte line per lane for CH = 16) and stores each chunk with
+// unit-stride lanes.  Items of segment 0 (the side head, whole waves of it)
+// store directly.  Needs hi - K >= log2 LANES.
+template <int K>
+struct MpBwdStage {
+  static constexpr int R = 1 << K;
+  static constexpr int CH = R < 16 ? R : 16;
+  static constexpr int ROW = CH + 1;  // padded row of one lane's chunk
+};
+
+template <int K, int LANES, typename RP, typename WP, typename SP, class WSync>
+QFT_HD void mp_bwd_wave_item(RP Win, WP Wout, SP ws, int logn, int hi, int64_t i, int lane,
+                             WSync wsync) {
+  using St = MpBwdStage<K>;
+  constexpr int R = St::R, CH = St::CH, ROW = St::ROW;
+  const int lgside = logn - 1;
+  const int lgItems = lgside - K;
+  const int lgG = hi - K;
+  const int64_t si = i >> lgItems;
+  const int item = (int)(i & ((1 << lgItems) - 1));
+  const int j = item >> lgG;
+  if (j == 0) {  // uniform over the wave
+    mp_bwd_group_item<K>(Win, Wout, logn, hi, i);
+    return;
+  }
+  const int ii = item & ((1 << lgG) - 1);
+  float2 y[R];
+  if (si & 1) bwd_group_load<K, true>(Win + (si << lgside), 1 << hi, j, ii, y);
+  else bwd_group_load<K, false>(Win + (si << lgside), 1 << hi, j, ii, y);
+  // lane 0's outputs start here, lane l's at + l * R
+  auto out = Wout + (si << lgside) + ((int64_t)j << hi) + ((int64_t)(ii - lane) << K);
+#pragma unroll
+  for (int c = 0; c < R / CH; ++c) {
+#pragma unroll
+    for (int e = 0; e < CH; ++e) ws[lane * ROW + e] = y[c * CH + e];
+    wsync();
+#pragma unroll
+    for (int r = 0; r < CH; ++r) {
+      const int f = r * LANES + lane;  // cell f of the chunk: lane f / CH, output f % CH
+      out[(f / CH) * R + c * CH + (f % CH)] = (float2)ws[(f / CH) * ROW + (f % CH)];
+    }
+    wsync();
+  }
+}
+
 // ===========================================================================
 // Compile-time specialised sweeps.  Sizes, round schedule and the thread ->
 // group mapping are template parameters, so that index arithmetic folds into

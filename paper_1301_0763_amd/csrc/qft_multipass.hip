@@ -41,56 +41,19 @@ __global__ __launch_bounds__(MP_BLOCK) void mp_fwd_kernel(float2* W, int logn, i
   QFT_GRID_STRIDE(i, (2 * batch) << (logn - K - 2)) mp_fwd_item<K>(W, logn, hi, sec, i);
 }
 
-// Backward rounds 2^(hi-K+1) .. 2^hi.  An item of a segment j >= 1 computes
-// 2^K consecutive outputs, so storing them straight from each lane would
-// spread every store instruction over 64 runs.  A segment holds 2^(hi-K) >=
-// 64 items, so the 64 items of a wavefront belong to one segment of one side
-// and their outputs are 64 * 2^K consecutive cells: the wave passes them
-// through LDS in chunks of CH outputs per lane (a 128-byte line per lane for
-// CH = 16) and stores each chunk with unit-stride lanes.  Items of segment 0
-// (the side head, a whole wave's worth at a time) store directly.  The
+// Backward rounds 2^(hi-K+1) .. 2^hi, one wavefront's 64 items at a time
+// (mp_bwd_wave_item); each wave stages its outputs in its own LDS rows.  The
 // launch guarantees hi - K >= 6 and a multiple of MP_BLOCK items.
 template <int K>
 __global__ __launch_bounds__(MP_BLOCK) void mp_bwd_kernel(const float2* Win, float2* Wout,
                                                           int logn, int64_t batch, int hi) {
-  constexpr int R = 1 << K;
-  constexpr int CH = R < 16 ? R : 16;
-  constexpr int ROW = CH + 1;  // padded row of one lane's chunk
+  constexpr int ROW = MpBwdStage<K>::ROW;
   __shared__ float2 stage[MP_BLOCK * ROW];
   const int lane = (int)threadIdx.x & (kWave - 1);
   float2* ws = stage + ((int)threadIdx.x - lane) * ROW;
-  const int lgside = logn - 1;
-  const int lgItems = lgside - K;
-  const int lgG = hi - K;
-  const int64_t total = (2 * batch) << lgItems;
-  for (int64_t b = (int64_t)blockIdx.x * MP_BLOCK; b < total; b += (int64_t)gridDim.x * MP_BLOCK) {
-    const int64_t i = b + threadIdx.x;
-    const int64_t si = i >> lgItems;
-    const int item = (int)(i & ((1 << lgItems) - 1));
-    const int j = item >> lgG;
-    if (j == 0) {  // uniform over the wave
-      mp_bwd_group_item<K>(Win, Wout, logn, hi, i);
-      continue;
-    }
-    const int ii = item & ((1 << lgG) - 1);
-    float2 y[R];
-    if (si & 1) bwd_group_load<K, true>(Win + (si << lgside), 1 << hi, j, ii, y);
-    else bwd_group_load<K, false>(Win + (si << lgside), 1 << hi, j, ii, y);
-    // outputs of lane 0 of the wave start here; lane l's at + l * R
-    float2* out = Wout + (si << lgside) + ((int64_t)j << hi) + ((int64_t)(ii - lane) << K);
-#pragma unroll
-    for (int c = 0; c < R / CH; ++c) {
-#pragma unroll
-      for (int e = 0; e < CH; ++e) ws[lane * ROW + e] = y[c * CH + e];
-      DevWaveSync{}();
-#pragma unroll
-      for (int r = 0; r < CH; ++r) {
-        const int f = r * kWave + lane;  // cell f of the wave's chunk: lane f / CH, output f % CH
-        out[(f / CH) * R + c * CH + (f % CH)] = ws[(f / CH) * ROW + (f % CH)];
-      }
-      DevWaveSync{}();
-    }
-  }
+  const int64_t total = (2 * batch) << (logn - 1 - K);
+  for (int64_t b = (int64_t)blockIdx.x * MP_BLOCK; b < total; b += (int64_t)gridDim.x * MP_BLOCK)
+    mp_bwd_wave_item<K, kWave>(Win, Wout, ws, logn, hi, b + threadIdx.x, lane, DevWaveSync{});
 }
 
 // E and Wout may be the same buffer (see mp_chain_item).

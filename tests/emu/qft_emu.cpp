@@ -312,7 +312,7 @@ struct EmuMultipass {
   float2* cur;
   float2* oth;
   int64_t cells;
-  Tracker gtr{1};
+  Tracker gtr{64};  // one log per emulated lane
   int64_t races = 0;
   template <class F>
   void items(int64_t total, F f) {
@@ -377,8 +377,26 @@ struct EmuMultipass {
   }
   template <int K>
   void bwd_k(int hi) {
-    items((2 * batch) << (logn - 1 - K),
-          [&](int64_t i) { qftk::mp_bwd_group_item<K>(G(cur), G(oth), logn, hi, i); });
+    const int64_t total = (2 * batch) << (logn - 1 - K);
+    if (hi - K >= 6 && logn - 1 - K >= 6) {
+      // as the GPU runs it: 64-lane wavefronts staging their outputs in LDS
+      constexpr int ROW = qftk::MpBwdStage<K>::ROW;
+      for (int64_t w = 0; w < total / 64; ++w) {
+        std::vector<float2> lds(64 * ROW);
+        Tracker ltr(64);
+        TPtr L{lds.data(), 0, &ltr, 64 * ROW};
+        run_workgroup(64, ltr, [&](int tid, auto, auto wsync) {
+          tl_actor = w * 64 + tid;  // unique over the pass
+          qftk::mp_bwd_wave_item<K, 64>(G(cur), G(oth), L, logn, hi, w * 64 + tid, tid, wsync);
+        });
+        races += ltr.races;
+        if (ltr.oob) races = -1000000;
+      }
+      gtr.end_phase();
+    } else {
+      items(total,
+            [&](int64_t i) { qftk::mp_bwd_group_item<K>(G(cur), G(oth), logn, hi, i); });
+    }
     std::swap(cur, oth);
   }
   void bwd(int K, int hi) {
