@@ -117,7 +117,8 @@ qft_status qft_plan_info(qft_plan_t plan, int64_t* total_points, int64_t* algo_b
  * Schedules.  A plan holds one or more schedules, each a list of persistent
  * tile-kernel launches ("groups") that says which transform sizes run with
  * which tile size: tiles of 2^12 cells (256 threads, 4 workgroups per CU),
- * 2^13 (512 threads, 2 per CU) or 2^14 (1024 threads, 1 per CU), and how
+ * 2^13 (512 threads, 2 per CU) or 2^14 (1024 threads, 1 per CU; a uniform
+ * batch of N = 2^13 or 2^14 runs 256 or 512 threads, 32 cells each), and how
  * the launch covers its tiles: a resident grid whose workgroups stride over
  * the tile list (persistent), or one workgroup per tile (name suffix
  * "/all").  Uniform plans with N <= 2^14 have one schedule per tile size

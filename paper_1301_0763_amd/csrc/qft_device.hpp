@@ -782,9 +782,9 @@ QFT_HD void bwd_chunk_s(WP W, int tid, Sync sync, WSync wsync) {
   constexpr int lgGroups = LGS - K;
   constexpr int total = Map::total;
   constexpr int NI = Map::NI;
-  // the R <= 8 outputs of an item are a run inside one padding block (sides
+  // the R <= 16 outputs of an item are a run inside one padding block (sides
   // start on a block boundary)
-  static_assert(K <= 3, "runs of at most 8 cells");
+  static_assert(R <= kRowCells, "runs of at most one row unit");
   float2 y[NI][R];
 #pragma unroll
   for (int it = 0; it < NI; ++it) {
@@ -824,20 +824,25 @@ QFT_HD void bwd_chunk_s(WP W, int tid, Sync sync, WSync wsync) {
 }
 
 // Rounds per LDS pass (KC) of the forward and backward chunks, and fused
-// innermost rounds (KT) of the tail: KT = 4 where it saves a pass, i.e. when
-// the rounds above the tail, TOP - 4, are a multiple of KC.
-constexpr int QFT_KC = 3;
-QFT_HD constexpr int sweep_tail_rounds(int top) {
-  return top < 4 ? top : ((top - 4) % QFT_KC == 0 ? 4 : 3);
+// innermost rounds (KT) of the tail.  A forward chunk of K rounds holds a
+// closed group of 2^(K+1) cells in one thread, so KC = 3 with 16 cells per
+// thread and KC = 4 with 32.  The tail takes KC + 1 rounds where that saves
+// a pass (the rounds above it a multiple of KC), else KC.
+template <int NS, int LGS, int NT>
+QFT_HD constexpr int sweep_kc() {
+  return ((NS << LGS) / NT) >= 32 ? 4 : 3;
+}
+QFT_HD constexpr int sweep_tail_rounds(int top, int kc) {
+  return top <= kc ? top : ((top - kc - 1) % kc == 0 ? kc + 1 : kc);
 }
 
 // Whether the LDS pass that follows the forward chunk ending at round 2^HI
 // (the next forward chunk, else the tail of KT rounds) stays in each wave's
 // cells (PassMap).
-template <int HI, int KT, int LGS, int NS, int NT, int WAVE>
+template <int HI, int KT, int KC, int LGS, int NS, int NT, int WAVE>
 QFT_HD constexpr bool fwd_next_local() {
   if constexpr (HI > KT) {
-    constexpr int K = cmin<QFT_KC, HI - KT>::v;
+    constexpr int K = cmin<KC, HI - KT>::v;
     return PassMap<NS, LGS, NT, WAVE, K + 1, HI>::local;
   } else {
     return PassMap<NS, LGS, NT, WAVE, KT, KT>::local;
@@ -846,24 +851,24 @@ QFT_HD constexpr bool fwd_next_local() {
 
 // forward chunks for rounds (KT, HI], top down, each followed by the
 // ordering the next pass needs
-template <int HI, int KT, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0, class Sync,
-          class WSync, typename WP>
+template <int HI, int KT, int KC, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0,
+          class Sync, class WSync, typename WP>
 QFT_HD void fwd_rounds_s(WP W, const float* sec, int tid, Sync sync, WSync wsync) {
   if constexpr (HI > KT) {
-    constexpr int K = cmin<QFT_KC, HI - KT>::v;
+    constexpr int K = cmin<KC, HI - KT>::v;
     fwd_chunk_s<K, HI, LGS, NS, NT, WAVE, MODE, SKIP0>(W, sec, tid);
     pass_sync<PassMap<NS, LGS, NT, WAVE, K + 1, HI>::local &&
-              fwd_next_local<HI - K, KT, LGS, NS, NT, WAVE>()>(sync, wsync);
-    fwd_rounds_s<HI - K, KT, LGS, NS, NT, WAVE, MODE, SKIP0>(W, sec, tid, sync, wsync);
+              fwd_next_local<HI - K, KT, KC, LGS, NS, NT, WAVE>()>(sync, wsync);
+    fwd_rounds_s<HI - K, KT, KC, LGS, NS, NT, WAVE, MODE, SKIP0>(W, sec, tid, sync, wsync);
   }
 }
 
 // Whether the backward chunk starting at round 2^LO (if LO <= TOP) stays in
 // each wave's cells; past the last chunk the caller's next stage does not.
-template <int LO, int TOP, int LGS, int NS, int NT, int WAVE>
+template <int LO, int TOP, int KC, int LGS, int NS, int NT, int WAVE>
 QFT_HD constexpr bool bwd_local() {
   if constexpr (LO <= TOP) {
-    constexpr int K = cmin<QFT_KC, TOP - LO + 1>::v;
+    constexpr int K = cmin<KC, TOP - LO + 1>::v;
     return PassMap<NS, LGS, NT, WAVE, K, LO + K - 1>::local;
   } else {
     return false;
@@ -872,14 +877,14 @@ QFT_HD constexpr bool bwd_local() {
 
 // backward chunks for rounds [LO, TOP], bottom up; the last one ends with a
 // workgroup barrier
-template <int LO, int TOP, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0, class Sync,
-          class WSync, typename WP>
+template <int LO, int TOP, int KC, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0,
+          class Sync, class WSync, typename WP>
 QFT_HD void bwd_rounds_s(WP W, int tid, Sync sync, WSync wsync) {
   if constexpr (LO <= TOP) {
-    constexpr int K = cmin<QFT_KC, TOP - LO + 1>::v;
+    constexpr int K = cmin<KC, TOP - LO + 1>::v;
     bwd_chunk_s<K, LO, LGS, NS, NT, WAVE, MODE, SKIP0,
-                bwd_local<LO + K, TOP, LGS, NS, NT, WAVE>()>(W, tid, sync, wsync);
-    bwd_rounds_s<LO + K, TOP, LGS, NS, NT, WAVE, MODE, SKIP0>(W, tid, sync, wsync);
+                bwd_local<LO + K, TOP, KC, LGS, NS, NT, WAVE>()>(W, tid, sync, wsync);
+    bwd_rounds_s<LO + K, TOP, KC, LGS, NS, NT, WAVE, MODE, SKIP0>(W, tid, sync, wsync);
   }
 }
 
@@ -890,12 +895,13 @@ template <int TOP, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0, clas
           class WSync, typename WP>
 QFT_HD void sweeps_s(WP W, const float* sec, int tid, Sync sync, WSync wsync) {
   if constexpr (TOP >= 1) {
-    constexpr int KT = sweep_tail_rounds(TOP);
-    fwd_rounds_s<TOP, KT, LGS, NS, NT, WAVE, MODE, SKIP0>(W, sec, tid, sync, wsync);
+    constexpr int KC = sweep_kc<NS, LGS, NT>();
+    constexpr int KT = sweep_tail_rounds(TOP, KC);
+    fwd_rounds_s<TOP, KT, KC, LGS, NS, NT, WAVE, MODE, SKIP0>(W, sec, tid, sync, wsync);
     tail_chunk_s<KT, LGS, NS, NT, WAVE, MODE, SKIP0>(W, sec, tid);
     pass_sync<PassMap<NS, LGS, NT, WAVE, KT, KT>::local &&
-              bwd_local<KT + 1, TOP, LGS, NS, NT, WAVE>()>(sync, wsync);
-    bwd_rounds_s<KT + 1, TOP, LGS, NS, NT, WAVE, MODE, SKIP0>(W, tid, sync, wsync);
+              bwd_local<KT + 1, TOP, KC, LGS, NS, NT, WAVE>()>(sync, wsync);
+    bwd_rounds_s<KT + 1, TOP, KC, LGS, NS, NT, WAVE, MODE, SKIP0>(W, tid, sync, wsync);
   }
 }
 

@@ -33,12 +33,20 @@ constexpr int kWave = 64;
 constexpr int kPad = 4;
 
 // Tile kernels with tiles of 2^tl cells (10 <= tl <= 14): 16 cells per
-// thread (64 to 1024 threads), and as many resident workgroups per CU as the
+// thread (64 to 1024 threads; 32 per thread for one transform of 2^13 or 2^14
+// points, tile_threads_one), and as many resident workgroups per CU as the
 // LDS (2^tl padded float2 cells out of 160 KiB) and the four waves per SIMD
 // of the persistent kernel allow.
 constexpr int kMinTileLog2 = 10;
 constexpr int kMaxTileLog2 = 14;
 constexpr int tile_threads(int tl) { return (1 << tl) / 16; }
+// A tile that holds one transform of 2^13 or 2^14 points runs 32 cells per
+// thread: four rounds per LDS pass instead of three (sweep_kc), which saves
+// two of its seven round passes.  At 2^12 it would save none and halve the
+// waves.
+constexpr int tile_threads_one(int logn, int tl) {
+  return (logn == tl && tl >= 13) ? (1 << tl) / 32 : (1 << tl) / 16;
+}
 constexpr int tile_wgs_per_cu(int tl) {
   return tl <= 10 ? 16 : (tl == 11 ? 8 : (tl == 12 ? 4 : (tl == 13 ? 2 : 1)));
 }

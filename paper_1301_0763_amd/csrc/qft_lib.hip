@@ -246,13 +246,13 @@ qft_status launch_twopass(const void* in, void* out, int log2n, int64_t batch, c
   if (blocks_a > 0x7fffffff) return QFT_ERROR_INVALID_VALUE;
   const unsigned gb = grid_for(batch << (log2n - 3), 256);
   if (log2n == 16) {
-    hipLaunchKernelGGL((qftk::tp_a2_kernel<13, 1024, DT, SWAP>), dim3((unsigned)(blocks_a / 2)),
-                       dim3(1024), 0, st, x, W, batch, sec);
+    hipLaunchKernelGGL((qftk::tp_a2_kernel<13, 512, DT, SWAP>), dim3((unsigned)(blocks_a / 2)),
+                       dim3(512), 0, st, x, W, batch, sec);
     hipLaunchKernelGGL((qftk::tp_b_kernel<13, DT, SWAP>), dim3(gb), dim3(256), 0, st,
                        (const float2*)W, X, batch);
   } else {
-    hipLaunchKernelGGL((qftk::tp_a2_kernel<12, 512, DT, SWAP>), dim3((unsigned)(blocks_a / 2)),
-                       dim3(512), 0, st, x, W, batch, sec);
+    hipLaunchKernelGGL((qftk::tp_a2_kernel<12, 256, DT, SWAP>), dim3((unsigned)(blocks_a / 2)),
+                       dim3(256), 0, st, x, W, batch, sec);
     hipLaunchKernelGGL((qftk::tp_b_kernel<12, DT, SWAP>), dim3(gb), dim3(256), 0, st,
                        (const float2*)W, X, batch);
   }

@@ -74,12 +74,13 @@ __global__ __launch_bounds__(MP_BLOCK) void mp_combine_kernel(IO io, const float
 #undef QFT_GRID_STRIDE
 
 // Segment pass: workgroup (t, j) takes segment j of both sides of transform
-// t (j = 0: the side heads and the top cell), 16 cells per thread.
+// t (j = 0: the side heads and the top cell), 32 cells per thread (four
+// rounds per LDS pass).
 template <int MC_LOG2, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void mp_segment_kernel(float2* W, int logn,
                                                            const float* sec) {
   constexpr int MC = 1 << MC_LOG2;
-  static_assert(2 * MC == 16 * BLOCK, "16 cells per thread");
+  static_assert(2 * MC == 32 * BLOCK, "32 cells per thread");
   __shared__ float2 Ll[padded_cells<kPad>(2 * MC + 1)];
   const PadPtr<kPad> L{Ll, 0};
   const int lgsegs = logn - 1 - MC_LOG2;
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(BLOCK) void mp_segment_kernel(float2* W, int logn,
 
 namespace {
 
-constexpr int kMpSegThreads = (2 << kMpSegLog2) / 16;
+constexpr int kMpSegThreads = (2 << kMpSegLog2) / 32;
 
 // Most forward rounds, backward rounds and chain levels per global pass
 // (QFT_MP_LEVELS=f,b,c overrides the defaults at build time).

@@ -21,7 +21,7 @@
 namespace qftk {
 
 template <int LOGN, int TL, int DT, bool SWAP>
-__global__ __launch_bounds__(tile_threads(TL)) void tile_kernel_u(const typename Store<DT>::T* x,
+__global__ __launch_bounds__(tile_threads_one(LOGN, TL)) void tile_kernel_u(const typename Store<DT>::T* x,
                                                                    typename Store<DT>::T* X,
                                                                    int64_t batch,
                                                                    const float* sec) {
@@ -31,8 +31,8 @@ __global__ __launch_bounds__(tile_threads(TL)) void tile_kernel_u(const typename
   const int64_t t0 = (int64_t)blockIdx.x * T;
   const int count = (int)min((int64_t)T, batch - t0);
   const ContigIO<DT, SWAP, LOGN> io(x + (t0 << LOGN), X + (t0 << LOGN));
-  tile_body_s<LOGN, T, tile_threads(TL), kWave>(io, W, count, sec, (int)threadIdx.x, DevSync{},
-                                                DevWaveSync{});
+  tile_body_s<LOGN, T, tile_threads_one(LOGN, TL), kWave>(io, W, count, sec, (int)threadIdx.x,
+                                                          DevSync{}, DevWaveSync{});
 }
 
 template <int TL, int DT, bool SWAP, int LOGN>
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(tile_threads(TL), 4) void tile_kernel_g(
 // Real-input kernels (KIND 0: rdft of real signals, KIND 1: DCT-0 and DST-0),
 // two real signals per transform slot, one workgroup per tile of T slots.
 template <int LOGN, int TL, int DT, int KIND>
-__global__ __launch_bounds__(tile_threads(TL)) void tile_kernel_r(RealArgs a, int64_t rows,
+__global__ __launch_bounds__(tile_threads_one(LOGN, TL)) void tile_kernel_r(RealArgs a, int64_t rows,
                                                                    int64_t slots,
                                                                    const float* sec) {
   constexpr int T = 1 << (TL - LOGN);
@@ -90,8 +90,8 @@ __global__ __launch_bounds__(tile_threads(TL)) void tile_kernel_r(RealArgs a, in
   if constexpr (KIND == 0) {
     using E = typename Store<DT>::T;
     const RealPairIO<DT, LOGN> io{(const R*)a.in0 + r0 * n, (E*)a.out0 + r0 * (h + 1), rows - r0};
-    tile_body_s<LOGN, T, tile_threads(TL), kWave>(io, W, count, sec, (int)threadIdx.x, DevSync{},
-                                                  DevWaveSync{});
+    tile_body_s<LOGN, T, tile_threads_one(LOGN, TL), kWave>(io, W, count, sec, (int)threadIdx.x,
+                                                            DevSync{}, DevWaveSync{});
   } else {
     const R* c = (const R*)a.in0;
     const R* d = (const R*)a.in1;
@@ -100,8 +100,8 @@ __global__ __launch_bounds__(tile_threads(TL)) void tile_kernel_r(RealArgs a, in
     const DctDstIO<DT, LOGN> io{c ? c + r0 * (h + 1) : nullptr, d ? d + r0 * (h - 1) : nullptr,
                                 C ? C + r0 * (h + 1) : nullptr, S ? S + r0 * (h - 1) : nullptr,
                                 rows - r0};
-    tile_body_s<LOGN, T, tile_threads(TL), kWave>(io, W, count, sec, (int)threadIdx.x, DevSync{},
-                                                  DevWaveSync{});
+    tile_body_s<LOGN, T, tile_threads_one(LOGN, TL), kWave>(io, W, count, sec, (int)threadIdx.x,
+                                                            DevSync{}, DevWaveSync{});
   }
 }
 
@@ -112,7 +112,7 @@ hipError_t launch_real_n(const TileGroup& g, const RealArgs& a, const float* sec
     if (g.ulog2n != LOGN) return launch_real_n<DT, TL, KIND, LOGN + 1>(g, a, sec, st);
     if constexpr ((LOGN < kMinTileLog2 ? kMinTileLog2 : LOGN) == TL) {
       hipLaunchKernelGGL((tile_kernel_r<LOGN, TL, DT, KIND>), dim3((unsigned)g.ntiles),
-                         dim3(tile_threads(TL)), 0, st, a, g.rows, g.ubatch, sec);
+                         dim3(tile_threads_one(LOGN, TL)), 0, st, a, g.rows, g.ubatch, sec);
       return hipGetLastError();
     }
   }
@@ -140,7 +140,8 @@ hipError_t launch_uniform(const TileGroup& g, const void* in, void* out, const f
     if (g.ulog2n != LOGN) return launch_uniform<DT, TL, SWAP, LOGN + 1>(g, in, out, sec, st);
     if constexpr ((LOGN < kMinTileLog2 ? kMinTileLog2 : LOGN) == TL) {
       hipLaunchKernelGGL((tile_kernel_u<LOGN, TL, DT, SWAP>), dim3((unsigned)g.ntiles),
-                         dim3(tile_threads(TL)), 0, st, (const E*)in, (E*)out, g.ubatch, sec);
+                         dim3(tile_threads_one(LOGN, TL)), 0, st, (const E*)in, (E*)out,
+                         g.ubatch, sec);
       return hipGetLastError();
     }
   }

@@ -203,13 +203,18 @@ void run_workgroup(int nthr, Tracker& tr, F fn) {
 
 
 // The specialised tile kernel exactly as launched on the GPU: LOGN <= 10 uses
-// 2^10-cell tiles of 64 threads, larger LOGN a tile of 2^LOGN cells with 16
-// cells per thread (128 .. 1024 threads).
-template <int DT, bool SWAP, int LOGN>
-int tile_s_impl(const void* x, void* X, int Tact, const float* sec, const int64_t* offs) {
+// 2^10-cell tiles of 64 threads, larger LOGN a tile of 2^LOGN cells.  The
+// uniform kernel runs a single transform of 2^13 or 2^14 points with 32
+// cells per thread, every other tile (and the uneven kernel) with 16.
+template <int LOGN, int TL>
+constexpr int emu_tile_threads(bool uneven) {
+  return (!uneven && LOGN == TL && TL >= 13) ? (1 << TL) / 32 : (1 << TL) / 16;
+}
+
+template <int DT, bool SWAP, int LOGN, int NT>
+int tile_s_run(const void* x, void* X, int Tact, const float* sec, const int64_t* offs) {
   using E = typename qftk::Store<DT>::T;
   constexpr int TL = LOGN <= 10 ? 10 : LOGN;
-  constexpr int NT = (1 << TL) / 16;
   constexpr int T = 1 << (TL - LOGN);
   if (Tact < 1 || Tact > T) return -2;
   const int64_t cells = (int64_t)T << LOGN;
@@ -228,6 +233,13 @@ int tile_s_impl(const void* x, void* X, int Tact, const float* sec, const int64_
   return tr.oob ? -100 : (int)tr.races;
 }
 
+template <int DT, bool SWAP, int LOGN>
+int tile_s_impl(const void* x, void* X, int Tact, const float* sec, const int64_t* offs) {
+  constexpr int TL = LOGN <= 10 ? 10 : LOGN;
+  if (offs) return tile_s_run<DT, SWAP, LOGN, emu_tile_threads<LOGN, TL>(true)>(x, X, Tact, sec, offs);
+  return tile_s_run<DT, SWAP, LOGN, emu_tile_threads<LOGN, TL>(false)>(x, X, Tact, sec, offs);
+}
+
 // One workgroup of the real-input tile kernel: KIND 0 = rdft of `rows` real
 // signals (two per transform slot), 1 = DCT-0/DST-0; rows <= 2 T.
 template <int DT, int LOGN, int KIND>
@@ -236,7 +248,7 @@ int tile_real_impl(int64_t rows, const void* in0, const void* in1, void* out0, v
   using R = typename qftk::RStore<DT>::T;
   using E = typename qftk::Store<DT>::T;
   constexpr int TL = LOGN <= 10 ? 10 : LOGN;
-  constexpr int NT = (1 << TL) / 16;
+  constexpr int NT = emu_tile_threads<LOGN, TL>(false);
   constexpr int T = 1 << (TL - LOGN);
   const int slots = (int)((rows + 1) / 2);
   if (rows < 1 || slots > T) return -2;
@@ -344,9 +356,9 @@ struct EmuMultipass {
   }
   template <int MC_LOG2>
   void segment_mc() {
-    // the GPU's 16 cells per thread for 2^12-cell segments, else <= 32
+    // the GPU's 32 cells per thread for 2^12-cell segments, else <= 32 threads
     constexpr int MC = 1 << MC_LOG2;
-    constexpr int NT = MC_LOG2 >= 12 ? (2 * MC) / 16 : (MC < 32 ? MC : 32);
+    constexpr int NT = MC_LOG2 >= 12 ? (2 * MC) / 32 : (MC < 32 ? MC : 32);
     const int segs = 1 << (logn - 1 - MC_LOG2);
     for (int64_t b = 0; b < batch * segs; ++b) {
       const int64_t t = b / segs;
@@ -517,9 +529,9 @@ template <int DT, bool SWAP, int MC_LOG2>
 int twopass_mc(const void* x, void* X, int64_t batch) {
   using E = typename qftk::Store<DT>::T;
   constexpr int MC = 1 << MC_LOG2;
-  // threads per workgroup: the GPU's (16 cells per thread: 512 for 2^12-cell
-  // segments, 1024 for 2^13), else <= 32
-  constexpr int NT = MC_LOG2 >= 12 ? (2 * MC) / 16 : (MC < 32 ? MC : 32);
+  // threads per workgroup: the GPU's (32 cells per thread: 256 for 2^12-cell
+  // segments, 512 for 2^13), else <= 32
+  constexpr int NT = MC_LOG2 >= 12 ? (2 * MC) / 32 : (MC < 32 ? MC : 32);
   constexpr int logn = MC_LOG2 + 3;
   const int64_t cells = batch << logn;
   std::vector<float> sec = secants(logn);
