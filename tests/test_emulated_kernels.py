@@ -153,7 +153,7 @@ def test_two_pass_small(emu, mc_log2, swap):
 @pytest.mark.slow
 def test_two_pass_library_size(emu):
     """N = 2^15 and 2^16 with the library's 2^12- and 2^13-cell segments
-    (512 and 1024 threads, as launched)."""
+    (256 and 512 threads of 32 cells, as launched)."""
     for mc in (12, 13):
         x = workloads.normal(15, (1, 8 << mc))
         races, out = run_tp(emu, x, mc)
@@ -165,8 +165,8 @@ def test_two_pass_library_size(emu):
 def test_specialised_tile_as_launched(emu, logn):
     """The compile-time specialised tile kernel with the GPU's own tile size
     and thread count (2^10-cell tiles of 64 threads up to N = 2^10, then one
-    transform per tile with 128 .. 1024 threads), on a full tile and on a
-    ragged last tile."""
+    transform per tile with 128 or 256 threads of 16 cells, or 256 or 512 of
+    32 cells for 2^13 and 2^14), on a full tile and on a ragged last tile."""
     N = 1 << logn
     T = max(1, 1024 // N)  # transforms per tile: 2^max(10, logn) cells
     for Tact in sorted({T, max(1, T // 2 - 1)}):
