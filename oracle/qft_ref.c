@@ -12,7 +12,10 @@
  * (eq. qft_0D).  Build with -ffp-contract=off so that no multiply is fused
  * with an add.  Temporaries come from a per-thread workspace of 12N doubles
  * (a bump allocator; the deepest call chain needs about 7N), so the recursion
- * never calls malloc.
+ * never calls malloc.  The secants 1/(2 cos(theta n)) of every periodization
+ * are evaluated once per call of an entry point into a table (the same
+ * expression, so the same FP64 values as evaluating them in place), slice P
+ * (odd n = 2j+1 < P/4, j < P/8) at offset P/8 - 2 for P >= 16.
  *
  * Readings of the paper (same as the Python oracle): eq. qft_38B is applied
  * as DCT[s_dc_oo](N/4-1) = DCT[s_dc_oe](N/4-2); dst_oo's special case is at
@@ -29,7 +32,25 @@
 typedef struct {
     double* base;
     size_t top;
+    const double* sec; /* secant table, see above */
+    double c8, s8;     /* cos(2 pi/8), sin(2 pi/8): the N = 8 base cases */
 } arena;
+
+/* Secant table for periodizations 16 .. Nmax: slice P at offset P/8 - 2,
+ * entry j = 1/(2 cos(2 pi (2j+1) / P)) (eq. qft_38A); Nmax/4 - 2 entries. */
+static double* secant_table(int Nmax) {
+    size_t n = Nmax >= 16 ? (size_t)Nmax / 4 - 2 : 1;
+    double* t = (double*)malloc(sizeof(double) * n);
+    if (!t) return NULL;
+    for (int P = 16; P <= Nmax; P *= 2) {
+        double* sl = t + P / 8 - 2;
+        for (int j = 0; j < P / 8; ++j) {
+            double n = 2.0 * j + 1.0;
+            sl[j] = 1.0 / (2.0 * cos(2.0 * M_PI * n / P));
+        }
+    }
+    return t;
+}
 
 static double* take(arena* a, size_t n) {
     double* p = a->base + a->top;
@@ -44,16 +65,14 @@ static void dst_ot(const double* s, int N, double* S, arena* a);
 static void dct_oo(const double* s, int N, double* S, arena* a) {
     int m = N / 8;
     if (N == 8) { /* definition: cos(2 pi / 8) */
-        S[0] = s[0] * cos(2.0 * M_PI / 8.0);
+        S[0] = s[0] * a->c8;
         return;
     }
     size_t mark = a->top;
     double* t = take(a, m);
     double* T = take(a, m);
-    for (int j = 0; j < m; ++j) { /* eq. qft_38A on odd n = 2j+1 */
-        double n = 2.0 * j + 1.0;
-        t[j] = s[j] * (1.0 / (2.0 * cos(2.0 * M_PI * n / N)));
-    }
+    const double* h = a->sec + N / 8 - 2;
+    for (int j = 0; j < m; ++j) t[j] = s[j] * h[j]; /* eq. qft_38A on odd n = 2j+1 */
     /* even-harmonic halving: s_A_dc_ot of periodization N/2 (Sec. 3.3) */
     dct_ot(t, N / 2, T, a);
     /* eq. qft_38C for odd k = 2j+1 <= N/4-3, corrected eq. qft_38B at N/4-1 */
@@ -115,16 +134,14 @@ static void dct(const double* s, int N, double* S, arena* a) {
 static void dst_oo(const double* s, int N, double* S, arena* a) {
     int m = N / 8;
     if (N == 8) {
-        S[0] = s[0] * sin(2.0 * M_PI / 8.0);
+        S[0] = s[0] * a->s8;
         return;
     }
     size_t mark = a->top;
     double* t = take(a, m);
     double* T = take(a, m);
-    for (int j = 0; j < m; ++j) {
-        double n = 2.0 * j + 1.0;
-        t[j] = s[j] * (1.0 / (2.0 * cos(2.0 * M_PI * n / N)));
-    }
+    const double* h = a->sec + N / 8 - 2;
+    for (int j = 0; j < m; ++j) t[j] = s[j] * h[j];
     dst_ot(t, N / 2, T, a); /* T[j] = DST[s_oe](2(j+1)) */
     S[0] = T[0];            /* k = 1: DST[s_oe](0) = 0 */
     for (int j = 1; j < m; ++j) S[j] = T[j - 1] + T[j];
@@ -233,6 +250,9 @@ static void cdft(const double* xr, const double* xi, int N, double* Xr, double* 
 int qft_ref_cdft(const double* x, double* X, int log2n, int64_t batch) {
     if (log2n < 1 || log2n > 26 || batch < 0) return -1;
     const int N = 1 << log2n;
+    double* sec = secant_table(N);
+    if (!sec) return -2;
+    const double c8 = cos(2.0 * M_PI / 8.0), s8 = sin(2.0 * M_PI / 8.0);
     int status = 0;
 #pragma omp parallel
     {
@@ -245,7 +265,7 @@ int qft_ref_cdft(const double* x, double* X, int log2n, int64_t batch) {
             double* xi = buf + N;
             double* Xr = buf + 2 * (size_t)N;
             double* Xi = buf + 3 * (size_t)N;
-            arena a = {buf + 4 * (size_t)N, 0};
+            arena a = {buf + 4 * (size_t)N, 0, sec, c8, s8};
 #pragma omp for schedule(dynamic, 1)
             for (int64_t b = 0; b < batch; ++b) {
                 const double* xb = x + 2 * (size_t)N * b;
@@ -258,7 +278,52 @@ int qft_ref_cdft(const double* x, double* X, int log2n, int64_t batch) {
             free(buf);
         }
     }
+    free(sec);
     return status;
+}
+
+/* Batched DCT-0 (dct on s_dc_tt, N/2+1 samples -> N/2+1 frequencies) when
+ * dst == 0, or DST-0 (dst on s_ds_tt, N/2-1 -> N/2-1) when dst != 0, of
+ * `batch` real signals of periodization N = 2^log2n, contiguous per signal
+ * (Sec. 5.2, eqs. qft_0B/qft_0C).  DST-0 needs N >= 4.  Returns as
+ * qft_ref_cdft. */
+int qft_ref_dct_dst(const double* s, double* S, int log2n, int64_t batch, int dst_side) {
+    if (log2n < 1 || log2n > 26 || batch < 0 || (dst_side && log2n < 2)) return -1;
+    const int N = 1 << log2n;
+    const int len = dst_side ? N / 2 - 1 : N / 2 + 1;
+    double* sec = secant_table(N);
+    if (!sec) return -2;
+    const double c8 = cos(2.0 * M_PI / 8.0), s8 = sin(2.0 * M_PI / 8.0);
+    int status = 0;
+#pragma omp parallel
+    {
+        double* buf = (double*)malloc(sizeof(double) * (size_t)N * 16);
+        if (!buf) {
+#pragma omp atomic write
+            status = -2;
+        } else {
+            arena a = {buf, 0, sec, c8, s8};
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t b = 0; b < batch; ++b) {
+                a.top = 0;
+                if (dst_side) dst(s + (size_t)len * b, N, S + (size_t)len * b, &a);
+                else dct(s + (size_t)len * b, N, S + (size_t)len * b, &a);
+            }
+            free(buf);
+        }
+    }
+    free(sec);
+    return status;
+}
+
+/* Sets the number of OpenMP threads of later calls (the single-thread CPU
+ * baseline uses 1). */
+void qft_ref_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 /* Number of threads the parallel region above uses. */

@@ -15,6 +15,7 @@ gfx950 kernels.
 Supported storage: complex64 (FP32) and complex32 / torch.chalf (FP16 storage,
 FP32 arithmetic).  N = 2^r with 1 <= r <= 24.
 """
+import collections
 import threading
 
 from . import _lib
@@ -210,13 +211,22 @@ class RealPlan:
             pass
 
 
+# Plans made by the convenience functions below.  A plan owns scratch memory
+# that one exec uses at a time (qft.h), so a cached plan serves one stream:
+# the stream is part of the key, and execs on two streams never share one.
 _cache = {}
 _cache_lock = threading.Lock()
+_PACKED_MAX = 4
+_packed = collections.OrderedDict()  # uneven plans, least recently used first
+
+
+def _dev_index(t):
+    return t.device.index if t.device.index is not None else _torch().cuda.current_device()
 
 
 def _real_plan(log2n, rows, t):
-    dev = t.device.index if t.device.index is not None else _torch().cuda.current_device()
-    key = ("real", log2n, rows, _real_code(t), dev)
+    dev = _dev_index(t)
+    key = ("real", log2n, rows, _real_code(t), dev, _stream_ptr(t.device))
     with _cache_lock:
         p = _cache.get(key)
         if p is None:
@@ -250,8 +260,8 @@ def _plan_for(x):
     N = x.shape[-1]
     log2n = _log2n(N)
     batch = x.numel() // N
-    dev = x.device.index if x.device.index is not None else _torch().cuda.current_device()
-    key = (log2n, batch, _dtype_code(x), dev)
+    dev = _dev_index(x)
+    key = (log2n, batch, _dtype_code(x), dev, _stream_ptr(x.device))
     with _cache_lock:
         p = _cache.get(key)
         if p is None:
@@ -273,11 +283,26 @@ def fft_adjoint(X):
 
 
 def fft_packed(values, log2n_list, plan=None):
-    """Forward DFTs of an uneven batch packed back to back in a 1-D tensor."""
+    """Forward DFTs of an uneven batch packed back to back in a 1-D tensor.
+    Without `plan`, the plan is kept for later calls with the same sizes, dtype,
+    device and stream (the last few such lists)."""
     values = values.contiguous()
     if plan is None:
-        dev = values.device.index if values.device.index is not None else 0
-        plan = UnevenPlan(log2n_list, _dtype_code(values), dev)
+        dev = _dev_index(values)
+        key = (tuple(int(v) for v in log2n_list), _dtype_code(values), dev,
+               _stream_ptr(values.device))
+        with _cache_lock:
+            plan = _packed.get(key)
+            if plan is None:
+                plan = UnevenPlan(key[0], key[1], dev)
+                _packed[key] = plan
+                while len(_packed) > _PACKED_MAX:
+                    _, old = _packed.popitem(last=False)
+                    # the evicted plan's last exec may still run on its stream
+                    _torch().cuda.synchronize(old.device)
+                    old.close()
+            else:
+                _packed.move_to_end(key)
     return plan.forward(values)
 
 

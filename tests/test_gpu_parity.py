@@ -1,9 +1,11 @@
 """GPU parity: the gfx950 library (through the C ABI) against the FP64 oracle.
 
-Tolerance (FP32 arithmetic): relative RMS error per signal (eq. qft_44 before
-averaging), ||X - X_ref||_2 / ||X_ref||_2 <= 1e-5 * log2 N, with X_ref the
-FP64 oracle evaluated on the FP32 input.  FP16 storage is bound by the output
-rounding (2^-11 relative per element) and is held to 1e-3.
+Every comparison goes through ``tests.parity.check`` (bounds derived there):
+per signal, the relative L2 error (eq. qft_44 before averaging) is at most
+1e-5 * log2 N, and every single bin is within c(n) * 1e-5 * log2 N * rms of
+the oracle's value, with X_ref the FP64 oracle evaluated on the stored input.
+FP16 storage adds the output rounding (2^-11 relative per element) to the bin
+bound and is held to 1e-3 in relative L2.
 """
 import ctypes
 import sys
@@ -15,6 +17,7 @@ import workloads
 from oracle import build as OB
 from oracle import direct as D
 from oracle import qft as Q
+from tests.parity import check, tol
 
 torch = pytest.importorskip("torch")
 import paper_1301_0763_amd as qft  # noqa: E402
@@ -27,10 +30,6 @@ DEV = "cuda:0"
 def say(msg):
     print(f"[gpu] {msg}", flush=True)
     sys.stdout.flush()
-
-
-def tol(logn):
-    return 1e-5 * logn
 
 
 def ref_fwd(x):
@@ -51,9 +50,8 @@ def test_c1_against_direct_dft():
     say("c1: N=1024 B=64 U[-1,1] seed 0, fwd vs O(N^2) DFT")
     x = workloads.make("c1")
     X = gpu_fwd(x)
-    err = D.relative_l2(X, D.dft(x.astype(np.complex128)))
-    say(f"c1 rel-L2 mean {err.mean():.3e} max {err.max():.3e}")
-    assert err.max() <= tol(10)
+    rel, worst = check(X, D.dft(x.astype(np.complex128)), 10, what="c1")
+    say(f"c1 rel-L2 max {rel:.3e}, worst bin {worst:.2f} of its bound")
 
 
 @pytest.mark.parametrize("logn", range(1, 15))
@@ -61,8 +59,7 @@ def test_all_tile_sizes(logn):
     B = 3 if logn > 10 else 5
     say(f"tile sizes: N=2^{logn} B={B}")
     x = workloads.uniform(1000 + logn, (B, 1 << logn))
-    err = D.relative_l2(gpu_fwd(x), ref_fwd(x))
-    assert err.max() <= tol(logn), err.max()
+    check(gpu_fwd(x), ref_fwd(x), logn, what=f"tile 2^{logn}")
 
 
 @pytest.mark.parametrize("logn,B", [(15, 3), (16, 2), (15, 200), (16, 130), (17, 2), (18, 1),
@@ -74,8 +71,7 @@ def test_multipass_sizes(logn, B):
     uses."""
     say(f"multi-pass: N=2^{logn} B={B}")
     x = workloads.normal(2000 + logn, (B, 1 << logn))
-    err = D.relative_l2(gpu_fwd(x), ref_fwd(x))
-    assert err.max() <= tol(logn), err.max()
+    check(gpu_fwd(x), ref_fwd(x), logn, what=f"multi-pass 2^{logn} x {B}")
 
 
 @pytest.mark.parametrize("logn,B", [(3, 4), (10, 6), (14, 2), (16, 2), (20, 1)])
@@ -85,11 +81,13 @@ def test_adjoint_and_round_trip(logn, B):
     N = 1 << logn
     y = gpu_fwd(x, adjoint=True)
     ref = np.conj(ref_fwd(np.conj(x.astype(np.complex128))))
-    assert D.relative_l2(y, ref).max() <= tol(logn)
-    # bwd(fwd(x)) = N x
+    check(y, ref, logn, what="adjoint")
+    # bwd(fwd(x)) = N x: two transforms, twice the error budget; relative L2
+    # only (the pull-back of the forward's error to x concentrates on a few
+    # samples, see tests/parity.py)
     xt = torch.from_numpy(x).to(DEV)
     rt = qft.fft_adjoint(qft.fft(xt)).cpu().numpy() / N
-    assert D.relative_l2(rt, x.astype(np.complex128)).max() <= 2 * tol(logn)
+    check(rt, x.astype(np.complex128), 2 * logn, what="round trip", per_bin=False)
     # dot-product test <F x, y> = <x, F^H y>
     z = workloads.uniform(3100 + logn, (B, N))
     Fx = gpu_fwd(x)
@@ -115,8 +113,7 @@ def test_fp16_storage_all_paths(logn, B):
         o = y.view(torch.float16).reshape(B, -1, 2).float().cpu().numpy().astype(np.float64)
         got = o[..., 0] + 1j * o[..., 1]
         ref = np.conj(ref_fwd(np.conj(xin))) if adj else ref_fwd(xin)
-        err = D.relative_l2(got, ref).max()
-        assert err <= 1e-3, (adj, err)
+        check(got, ref, logn, fp16=True, what=f"fp16 adjoint={adj}")
 
 
 def test_c2_full_size():
@@ -124,9 +121,8 @@ def test_c2_full_size():
     x = workloads.make("c2")
     X = gpu_fwd(x)
     ref = OB.cdft(x.astype(np.complex128))
-    err = D.relative_l2(X, ref)
-    say(f"c2 rel-L2 mean {err.mean():.3e} max {err.max():.3e}")
-    assert err.max() <= tol(16)
+    rel, worst = check(X, ref, 16, what="c2")
+    say(f"c2 rel-L2 max {rel:.3e}, worst bin {worst:.2f} of its bound")
     # independent spot check against the DFT definition on sampled bins
     bins = np.array([0, 1, 7, 4096, 32767, 32768, 32769, 65535])
     direct_vals = D.dft_bins(x[:2].astype(np.complex128), bins)
@@ -139,9 +135,8 @@ def test_c3_single_large():
     x, freqs, amps = workloads.make("c3")
     X = gpu_fwd(x)
     ref = OB.cdft(x.astype(np.complex128))
-    err = D.relative_l2(X, ref).max()
-    say(f"c3 rel-L2 {err:.3e} (target {tol(24):.1e})")
-    assert err <= tol(24)
+    rel, worst = check(X, ref, 24, what="c3")
+    say(f"c3 rel-L2 {rel:.3e} (target {tol(24):.1e}), worst bin {worst:.2f} of its bound")
     N = 1 << 24
     # closed form: |X(f_i)| ~ N a_i, far above the noise floor
     got = np.abs(X[0, freqs])
@@ -172,8 +167,8 @@ def _uneven(dtype):
         N = 1 << lg
         xs = np.stack([xin[off[i]:off[i] + N] for i in idx])
         gs = np.stack([got[off[i]:off[i] + N] for i in idx])
-        e = D.relative_l2(gs, OB.cdft(xs)).max()
-        worst = max(worst, e / (tol(lg) if dtype == "c32" else 1e-3))
+        rel, _ = check(gs, OB.cdft(xs), lg, fp16=dtype == "c16", what=f"c4 {dtype} 2^{lg}")
+        worst = max(worst, rel / (tol(lg) if dtype == "c32" else 1e-3))
     return worst
 
 
@@ -200,9 +195,8 @@ def test_c5_autograd_loss_gradient():
     x64 = x.astype(np.complex128)
     Xr = OB.cdft(x64)
     gref = 2 * np.conj(OB.cdft(np.conj(w * Xr)))
-    err = D.relative_l2(g, gref).max()
-    say(f"c5 grad rel-L2 {err:.3e}")
-    assert err <= 2 * tol(12)
+    rel, _ = check(g, gref, 2 * 12, what="c5 gradient")  # two transforms
+    say(f"c5 grad rel-L2 {rel:.3e}")
 
 
 def test_gradcheck_small_against_finite_differences():
@@ -235,7 +229,7 @@ def test_gradcheck_small_against_finite_differences():
                 zm = x64.copy(); zm[b, n] -= h * unit
                 d = (Lf(zp) - Lf(zm)) / (2 * h)
                 fd[b, n] += d if part == 0 else 1j * d
-    assert D.relative_l2(g, fd).max() <= 2 * tol(6)
+    check(g, fd, 2 * 6, what="gradcheck")
 
 
 def test_in_place_and_errors():
@@ -332,8 +326,7 @@ def test_uniform_and_uneven_kernels_agree(logn, B):
         up.schedule = i
         assert torch.equal(up.forward(flat).reshape(B, -1), ref), up.schedules[i]
     torch.cuda.synchronize()
-    err = D.relative_l2(ref.cpu().numpy(), ref_fwd(x)).max()
-    assert err <= tol(logn), err
+    check(ref.cpu().numpy(), ref_fwd(x), logn, what="uniform vs uneven")
     up.close()
 
 
@@ -392,8 +385,7 @@ def test_rdft_all_tile_sizes(logn):
     H = qft.rdft(torch.from_numpy(x).to(DEV))
     torch.cuda.synchronize()
     assert H.shape == (B, N // 2 + 1) and H.dtype == torch.complex64
-    err = D.relative_l2(H.cpu().numpy().astype(np.complex128), _rdft_ref(x)).max()
-    assert err <= tol(logn), err
+    check(H.cpu().numpy(), _rdft_ref(x), logn, what=f"rdft 2^{logn}")
 
 
 def test_rdft_matches_complex_path_and_fp16():
@@ -408,12 +400,12 @@ def test_rdft_matches_complex_path_and_fp16():
     torch.cuda.synchronize()
     h = H.cpu().numpy().astype(np.complex128)
     full = X.cpu().numpy().astype(np.complex128)[:, :(1 << logn) // 2 + 1]
-    assert D.relative_l2(h, full).max() <= tol(logn)
+    check(h, full, 2 * logn, what="rdft vs complex")  # both sides carry FP32 error
     H16 = qft.rdft(xt.half())
     torch.cuda.synchronize()
     h16 = H16.view(torch.float16).reshape(B, -1, 2).float().cpu().numpy()
     ref16 = _rdft_ref(x.astype(np.float16).astype(np.float64))
-    assert D.relative_l2(h16[..., 0] + 1j * h16[..., 1], ref16).max() < 1e-3
+    check(h16[..., 0] + 1j * h16[..., 1], ref16, logn, fp16=True, what="rdft fp16")
 
 
 @pytest.mark.parametrize("logn", [1, 2, 3, 6, 10, 13, 14])
@@ -433,11 +425,14 @@ def test_dct0_dst0(logn):
     C, S = plan.dct0_dst0(ct, dt_ if h > 1 else None)
     C1 = qft.dct0(ct)
     torch.cuda.synchronize()
-    assert D.relative_l2(C.cpu().numpy().astype(np.float64), refC).max() <= tol(logn)
+    check(C.cpu().numpy(), refC, logn, what="dct0")
     assert torch.equal(C, C1)
     if h > 1:
         refS = Q.dst(d.astype(np.float64), N, Q.Ops())
-        assert D.relative_l2(S.cpu().numpy().astype(np.float64), refS).max() <= tol(logn)
+        if h > 2:
+            check(S.cpu().numpy(), refS, logn, what="dst0")
+        else:  # one value, S(1) = d(1): an exact copy
+            assert np.array_equal(S.cpu().numpy().astype(np.float64), refS)
         assert torch.equal(qft.dst0(dt_), S)
         # in place: c -> C and d -> S in the input buffers
         qft.qft_exec_dct0_dst0(plan.handle, ct.data_ptr(), dt_.data_ptr(), ct.data_ptr(),
@@ -468,17 +463,79 @@ def test_real_plan_errors():
 @pytest.mark.parametrize("logn,B", [(15, 3), (16, 4), (18, 1)])
 def test_real_input_multipass_sizes(logn, B):
     """Real-input plans beyond a tile: the multi-pass path on transform slots
-    of two real signals, rdft and DCT-0/DST-0 against the oracle."""
+    of two real signals, rdft, DCT-0 and DST-0 against the oracle (the C copy
+    of the recursion for the DCT-0/DST-0 of every size)."""
     N, h = 1 << logn, 1 << (logn - 1)
     say(f"real multi-pass: N=2^{logn} B={B}")
     x = np.ascontiguousarray(workloads.normal(8000 + logn, (B, N)).real.astype(np.float32))
     H = qft.rdft(torch.from_numpy(x).to(DEV))
     torch.cuda.synchronize()
     ref = OB.cdft(x.astype(np.complex128))[:, :h + 1]
-    assert D.relative_l2(H.cpu().numpy().astype(np.complex128), ref).max() <= tol(logn)
+    check(H.cpu().numpy(), ref, logn, what=f"rdft 2^{logn}")
     c = np.ascontiguousarray(workloads.uniform(8100 + logn, (B, h + 1)).real.astype(np.float32))
+    d = np.ascontiguousarray(workloads.uniform(8200 + logn, (B, h - 1)).real.astype(np.float32))
     C = qft.dct0(torch.from_numpy(c).to(DEV))
+    S = qft.dst0(torch.from_numpy(d).to(DEV))
     torch.cuda.synchronize()
-    refC = Q.dct(c.astype(np.float64), N, Q.Ops()) if logn <= 16 else None
-    if refC is not None:
-        assert D.relative_l2(C.cpu().numpy().astype(np.float64), refC).max() <= tol(logn)
+    check(C.cpu().numpy(), OB.dct(c.astype(np.float64), N), logn, what=f"dct0 2^{logn}")
+    check(S.cpu().numpy(), OB.dst(d.astype(np.float64), N), logn, what=f"dst0 2^{logn}")
+
+
+def test_broadband_2p24():
+    """One N = 2^24 transform of N(0,1) samples: every bin carries a
+    comparable share of the energy, so the per-bin bound checks all 16.7 M
+    bins of the multi-pass path (the tones of c3 leave most bins near the
+    noise floor)."""
+    say("broadband: N=2^24 B=1 N(0,1) seed 24")
+    x = workloads.normal(24, (1, 1 << 24))
+    X = gpu_fwd(x)
+    rel, worst = check(X, OB.cdft(x.astype(np.complex128)), 24, what="broadband 2^24")
+    say(f"broadband 2^24 rel-L2 {rel:.3e}, worst bin {worst:.2f} of its bound")
+
+
+def test_uneven_with_long_transforms():
+    """An uneven plan whose transforms beyond a tile (2^15 and 2^16 two-pass,
+    2^17 multi-pass) sit at nonzero offsets between tile-sized ones, in every
+    schedule, forward and adjoint."""
+    sizes = [6, 12, 15, 16, 17, 6, 15, 9, 16]
+    say(f"uneven with long transforms: {sizes}")
+    off = np.concatenate([[0], np.cumsum([1 << s for s in sizes])])
+    vals = workloads.normal(4321, (int(off[-1]),))
+    plan = qft.UnevenPlan(sizes)
+    xt = torch.from_numpy(vals).to(DEV)
+    outs = []
+    for i in range(len(plan.schedules)):
+        plan.schedule = i
+        outs.append((plan.forward(xt), plan.adjoint(xt)))
+    torch.cuda.synchronize()
+    for f, b in outs[1:]:
+        assert torch.equal(f, outs[0][0]) and torch.equal(b, outs[0][1])
+    got_f = outs[0][0].cpu().numpy()
+    got_b = outs[0][1].cpu().numpy()
+    for i, lg in enumerate(sizes):
+        seg = vals[off[i]:off[i + 1]].astype(np.complex128)[None]
+        check(got_f[off[i]:off[i + 1]][None], OB.cdft(seg), lg, what=f"uneven #{i} 2^{lg}")
+        check(got_b[off[i]:off[i + 1]][None], np.conj(OB.cdft(np.conj(seg))), lg,
+              what=f"uneven adjoint #{i} 2^{lg}")
+    plan.close()
+
+
+def test_two_streams_share_no_scratch():
+    """fft() on two streams at once with the same shape (N = 2^16, a plan
+    with scratch memory): each stream gets a plan of its own, and both results
+    match the oracle."""
+    say("two streams, N=2^16 B=16")
+    xa = workloads.normal(61, (16, 1 << 16))
+    xb = workloads.normal(62, (16, 1 << 16))
+    ta, tb = torch.from_numpy(xa).to(DEV), torch.from_numpy(xb).to(DEV)
+    torch.cuda.synchronize()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = {}
+    for _ in range(3):
+        with torch.cuda.stream(sa):
+            outs["a"] = qft.fft(ta)
+        with torch.cuda.stream(sb):
+            outs["b"] = qft.fft(tb)
+    torch.cuda.synchronize()
+    check(outs["a"].cpu().numpy(), OB.cdft(xa.astype(np.complex128)), 16, what="stream a")
+    check(outs["b"].cpu().numpy(), OB.cdft(xb.astype(np.complex128)), 16, what="stream b")

@@ -122,3 +122,41 @@ def test_bins_and_adjoint():
     # F^H F = N I
     np.testing.assert_allclose(D.dft_adjoint(D.dft(x)), N * x, atol=1e-10)
     np.testing.assert_allclose(D.dft_adjoint(x), N * np.fft.ifft(x), atol=1e-11)
+
+
+# --- the accuracy measures used by every parity test -------------------------
+def test_relative_l2_hand_values():
+    """eq. qft_44 before averaging: ||S - S_exact||_2 / ||S_exact||_2 per
+    signal.  Hand values: a 10% scaling gives exactly 0.1; S_exact = (3, 4)
+    (norm 5) with one component off by 1 gives 1/5 (0.04 if the square root
+    were dropped); S = 2 S_exact gives 1 (0.5 if normalised by ||S||); S = 0
+    gives 1; one value per signal along the chosen axis."""
+    e = np.array([3.0 + 0j, 4.0])
+    assert D.relative_l2(1.1 * e, e) == pytest.approx(0.1, rel=1e-15, abs=0)
+    assert D.relative_l2(np.array([3.0, 5.0]), e) == pytest.approx(0.2, rel=1e-15)
+    assert D.relative_l2(2 * e, e) == pytest.approx(1.0, rel=1e-15)
+    assert D.relative_l2(np.zeros(2), e) == pytest.approx(1.0, rel=1e-15)
+    # complex parts: S_exact = (1, i), S = (1 + i, i) -> |i| / sqrt(2)
+    assert D.relative_l2(np.array([1 + 1j, 1j]), np.array([1, 1j])) == \
+        pytest.approx(1 / np.sqrt(2), rel=1e-15)
+    # per signal along the axis: rows (0.1, 1.0); along axis 0 (columns)
+    Sx = np.stack([1.1 * e, 2 * e])
+    Ex = np.stack([e, e])
+    np.testing.assert_allclose(D.relative_l2(Sx, Ex), [0.1, 1.0], rtol=1e-15)
+    np.testing.assert_allclose(D.relative_l2(Sx, Ex, axis=0),
+                               [np.sqrt(0.1 ** 2 + 1) / np.sqrt(2)] * 2, rtol=1e-15)
+
+
+def test_bin_errors_hand_values():
+    """|S(k) - S_exact(k)| / rms(S_exact): S_exact = (3, 4i) has rms
+    sqrt(12.5); an error of 1 in bin 1 gives (0, 1/sqrt(12.5)); relative_l2
+    is the root mean square of the bin errors."""
+    e = np.array([3.0 + 0j, 4.0j])
+    got = D.bin_errors(np.array([3.0, 5.0j]), e)
+    np.testing.assert_allclose(got, [0.0, 1 / np.sqrt(12.5)], rtol=1e-15)
+    rng = np.random.default_rng(3)
+    S = rng.standard_normal((4, 64)) + 1j * rng.standard_normal((4, 64))
+    E = rng.standard_normal((4, 64)) + 1j * rng.standard_normal((4, 64))
+    np.testing.assert_allclose(np.sqrt(np.mean(D.bin_errors(S, E) ** 2, -1)),
+                               D.relative_l2(S, E), rtol=1e-13)
+    assert D.bin_errors(S, E).shape == (4, 64)

@@ -183,6 +183,20 @@ def test_storage_size_checks_fire():
         Q.dst_oo(np.zeros(3), 32, Q.Ops())  # ds_oo at N=32 stores 4
 
 
+def test_conservation_check_fires():
+    """The Sec. 6.1 ln/lk conservation check rejects a child list that does
+    not hold exactly the parent's cells (eqs. qft_42/qft_43), and accepts the
+    ones the recursion uses."""
+    Q._conserved("dc_ot", 32, [("dc_oe", 32), ("dc_oo", 32)])
+    Q._conserved("dc_tt", 32, [("dc_et", 32), ("dc_ot", 32)])
+    with pytest.raises(AssertionError):  # one child missing
+        Q._conserved("dc_ot", 32, [("dc_oe", 32)])
+    with pytest.raises(AssertionError):  # a child at the wrong periodization
+        Q._conserved("dc_oo", 32, [("dc_ot", 32)])
+    with pytest.raises(AssertionError):  # the DST child list of a DCT parent
+        Q._conserved("dc_tt", 32, [("ds_et", 32), ("ds_ot", 32)])
+
+
 def test_table1_sizes():
     # a few rows of Table 1 transcribed as numbers (N = 64)
     N = 64
