@@ -76,11 +76,13 @@ QFT_HD float2 cscale(float2 a, float h) { return make_float2(a.x * h, a.y * h); 
 template <int DT> struct Store;
 template <> struct Store<0> {
   using T = float2;
+  static QFT_HD float2 cvt(T v) { return v; }
   static QFT_HD float2 ld(const T* p, int64_t i) { return p[i]; }
   static QFT_HD void st(T* p, int64_t i, float2 v) { p[i] = v; }
 };
 template <> struct Store<1> {
   using T = __half2;
+  static QFT_HD float2 cvt(T v) { return __half22float2(v); }
   static QFT_HD float2 ld(const T* p, int64_t i) { return __half22float2(p[i]); }
   static QFT_HD void st(T* p, int64_t i, float2 v) { p[i] = __float22half2_rn(v); }
 };
@@ -1948,52 +1950,6 @@ struct HeadSides {  // the head segments of pass A: DCT, DST and the top cell
   QFT_HD LP top(int) const { return L + 2 * mc; }
 };
 
-// Folded heap values of position q of segment j < 2 (both sides) straight
-// from x: c(n) = x(n) + x(N-n), d(n) = x(n) - x(N-n) with n = (N/4M)(2v+1)
-// for heap cell p = j MC + q in block M = 2^floor(log2 p), v = p - M; cell
-// 0 holds c(0) (its DST cell is unused).
-// Branch-free, so that the loads of all of a thread's positions are in
-// flight together: cell 0 loads x(0) and, unused, x(3N/4).
-template <int DT, bool SWAP, int MC_LOG2>
-QFT_HD void tp_gather01(const typename Store<DT>::T* xt, int j, int q, float2& vc, float2& vs) {
-  constexpr int MC = 1 << MC_LOG2;
-  constexpr int logn = MC_LOG2 + 3;
-  constexpr int N = 1 << logn;
-  const int p = j * MC + q;
-  const bool zero = p == 0;
-  const int pp = zero ? 1 : p;
-  const int lgM = 31 - __builtin_clz(pp);
-  const int v = pp - (1 << lgM);
-  const int n = (2 * v + 1) << (logn - 2 - lgM);
-  const float2 a = sw<SWAP>(Store<DT>::ld(xt, zero ? 0 : n));
-  const float2 b = sw<SWAP>(Store<DT>::ld(xt, N - n));
-  vc = zero ? a : cadd(a, b);                       // c(0) for cell 0
-  vs = zero ? make_float2(0.f, 0.f) : csub(a, b);
-}
-
-// Segments 2 and 3 (the halves of the block N/4 after its top forward round,
-// S = 2 MC: pair (q, 2MC-1-q), i.e. odd n = 2q+1 and its mirror N/2 - n) at
-// position q, both from the same four samples of x.
-template <int DT, bool SWAP, int MC_LOG2>
-QFT_HD void tp_gather23(const typename Store<DT>::T* xt, int q, const float* __restrict__ sec,
-                        float2& vc2, float2& vs2, float2& vc3, float2& vs3) {
-  constexpr int MC = 1 << MC_LOG2;
-  constexpr int logn = MC_LOG2 + 3;
-  constexpr int N = 1 << logn, h = N >> 1;
-  const int n = 2 * q + 1;
-  const float2 a0 = sw<SWAP>(Store<DT>::ld(xt, n));
-  const float2 b0 = sw<SWAP>(Store<DT>::ld(xt, N - n));
-  const float2 a1 = sw<SWAP>(Store<DT>::ld(xt, h - n));
-  const float2 b1 = sw<SWAP>(Store<DT>::ld(xt, h + n));
-  const float2 c0 = cadd(a0, b0), c1 = cadd(a1, b1);  // c(n), c(N/2-n)
-  const float2 d0 = csub(a0, b0), d1 = csub(a1, b1);  // d(n), d(N/2-n)
-  const float hs = sec[MC + q];
-  vc2 = cadd(c0, c1);
-  vs2 = csub(d0, d1);
-  vc3 = cscale(csub(c0, c1), hs);
-  vs3 = cscale(cadd(d0, d1), hs);
-}
-
 // Segment j of a transform heap wt with sides of h cells once both sides'
 // segment j is in LDS (DCT at L[0, MC), DST at L[MC, 2MC), for j = 0 the top
 // cell at L[2MC]): the remaining rounds, for the head the DCT-0/DST-0 chain
@@ -2026,6 +1982,99 @@ QFT_HD void tp_segment(GP wt, LP L, int j, int h, const float* sec, int tid, Syn
   if (j == 0 && tid == 0) wt[h] = (float2)L[2 * MC];  // D_{2MC}(MC): top cell
 }
 
+// The x samples pass A needs for segment j of one transform, as stored
+// (loaded by tp_load_a, folded into LDS by tp_fold_a):
+//   j = 0: x(n), x(N - n), n = 4m for the thread's items m, and x(N/2)
+//          (thread 0).  c(n), d(n) belong to heap cell M + (n >> (v + 1))
+//          with v = ctz(n) and M = N >> (v + 2), the odd-time block of
+//          periodization N / 2^v; item 0 is c(0) at cell 0 (it also loads
+//          x(N - 4), unused).  Walking the head's cells in order would read
+//          each block at its own stride (8 samples for the largest, up to
+//          N/4); walking m reads x at a stride of 4 samples and scatters
+//          into LDS instead;
+//   j = 1: x(n), x(N - n), n = 4q + 2 (heap cell MC + q, the block N/8);
+//   j >= 2: x(n), x(N - n), x(N/2 - n), x(N/2 + n), n = 2q + 1.
+template <int DT, int NI>
+struct TpRaw {
+  using T = typename Store<DT>::T;
+  T a[NI], b[NI], c[NI], d[NI];
+  T top;
+};
+
+template <int DT, int MC_LOG2, int NT>
+QFT_HD void tp_load_a(const typename Store<DT>::T* xt, int j, int tid,
+                      TpRaw<DT, (1 << MC_LOG2) / NT>& r) {
+  constexpr int MC = 1 << MC_LOG2;
+  constexpr int N = 8 * MC, h = 4 * MC;
+  constexpr int NI = MC / NT;
+  if (j < 2) {
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int q = tid + it * NT;
+      const int n = j == 0 ? 4 * q : 4 * q + 2;
+      r.a[it] = xt[n];
+      r.b[it] = xt[N - (n == 0 ? 4 : n)];
+    }
+    if (j == 0 && tid == 0) r.top = xt[h];
+  } else {
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int n = 2 * (tid + it * NT) + 1;
+      r.a[it] = xt[n];
+      r.b[it] = xt[N - n];
+      r.c[it] = xt[h - n];
+      r.d[it] = xt[h + n];
+    }
+  }
+}
+
+// Fold (and for j >= 2 the top forward round) of the loaded samples into the
+// LDS segments: DCT at L[0, MC), DST at L[MC, 2MC), the top cell at L[2MC].
+template <int DT, bool SWAP, int MC_LOG2, int NT, typename LP>
+QFT_HD void tp_fold_a(const TpRaw<DT, (1 << MC_LOG2) / NT>& r, int j, int tid,
+                      const float* __restrict__ sec, LP L) {
+  constexpr int MC = 1 << MC_LOG2;
+  constexpr int N = 8 * MC;
+  constexpr int NI = MC / NT;
+  using S = Store<DT>;
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int q = tid + it * NT;
+    const float2 a0 = sw<SWAP>(S::cvt(r.a[it])), b0 = sw<SWAP>(S::cvt(r.b[it]));
+    float2 vc, vs;
+    int cell = q;
+    if (j == 0) {
+      // head: n = 4q to heap cell M + (n >> (v + 1)), v = ctz(n), M = N >> (v + 2)
+      const bool zero = q == 0;
+      const int n = zero ? 4 : 4 * q;
+      const int v = __builtin_ctz((unsigned)n);
+      cell = zero ? 0 : (N >> (v + 2)) + (n >> (v + 1));
+      vc = zero ? a0 : cadd(a0, b0);                  // c(0) for cell 0
+      vs = zero ? make_float2(0.f, 0.f) : csub(a0, b0);
+    } else if (j == 1) {
+      vc = cadd(a0, b0);
+      vs = csub(a0, b0);
+    } else {
+      // segments 2 and 3: the halves of the block N/4 after its top forward
+      // round (S = 2 MC pairs odd n = 2q + 1 with N/2 - n)
+      const float2 a1 = sw<SWAP>(S::cvt(r.c[it])), b1 = sw<SWAP>(S::cvt(r.d[it]));
+      const float2 c0 = cadd(a0, b0), c1 = cadd(a1, b1);  // c(n), c(N/2-n)
+      const float2 d0 = csub(a0, b0), d1 = csub(a1, b1);  // d(n), d(N/2-n)
+      if (j == 2) {
+        vc = cadd(c0, c1);
+        vs = csub(d0, d1);
+      } else {
+        const float hs = sec[MC + q];
+        vc = cscale(csub(c0, c1), hs);
+        vs = cscale(cadd(d0, d1), hs);
+      }
+    }
+    L[cell] = vc;
+    L[MC + cell] = vs;
+  }
+  if (j == 0 && tid == 0) L[2 * MC] = sw<SWAP>(S::cvt(r.top));  // c(N/2)
+}
+
 // Pass A with both sides of one segment index j in the same workgroup: the
 // DCT and DST cells of a position come from the same x samples (c = a + b,
 // d = a - b), so x is gathered once for both.
@@ -2034,33 +2083,92 @@ template <int DT, bool SWAP, int MC_LOG2, int NT, int WAVE, class Sync, class WS
 QFT_HD void tp_pass_a2(const typename Store<DT>::T* xt, GP wt, LP L, int j, const float* sec,
                        int tid, Sync sync, WSync wsync) {
   constexpr int MC = 1 << MC_LOG2;
-  constexpr int h = 4 * MC;
-  constexpr int NI = MC / NT;  // positions per thread
-  float2 vc[NI], vs[NI];
-  // j is uniform over the workgroup: one branch around straight-line loads
-  if (j < 2) {
-#pragma unroll
-    for (int it = 0; it < NI; ++it)
-      tp_gather01<DT, SWAP, MC_LOG2>(xt, j, tid + it * NT, vc[it], vs[it]);
-  } else {
-#pragma unroll
-    for (int it = 0; it < NI; ++it) {
-      float2 c2, s2, c3, s3;
-      tp_gather23<DT, SWAP, MC_LOG2>(xt, tid + it * NT, sec, c2, s2, c3, s3);
-      vc[it] = j == 2 ? c2 : c3;
-      vs[it] = j == 2 ? s2 : s3;
-    }
+  TpRaw<DT, MC / NT> r;
+  tp_load_a<DT, MC_LOG2, NT>(xt, j, tid, r);
+  tp_fold_a<DT, SWAP, MC_LOG2, NT>(r, j, tid, sec, L);
+  tp_segment<MC_LOG2, NT, WAVE>(wt, L, j, 4 * MC, sec, tid, sync, wsync);
+}
+
+// Tile T of pass A: transform 8 (T / 32) + T % 8, segment (T / 8) % 4, so
+// that the four workgroups of a transform share T % 8, i.e. the XCD under
+// round-robin dispatch (and that XCD's L2 holds x for all four).
+QFT_HD int64_t tp_tile_transform(int64_t T) { return (T >> 5) * 8 + (T & 7); }
+QFT_HD int tp_tile_segment(int64_t T) { return (int)((T >> 3) & 3); }
+// The first tile at or after T on the workgroup's stride whose transform is
+// in the batch (the last group of eight transforms may be ragged).
+QFT_HD int64_t tp_next_tile(int64_t T, int64_t stride, int64_t ntiles, int64_t batch) {
+  while (T < ntiles && tp_tile_transform(T) >= batch) T += stride;
+  return T;
+}
+
+// An opaque copy: the compiler must treat v as changed here (no instruction
+// is emitted on the GPU).
+QFT_HD void launder(int& v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(v));
+#else
+  (void)v;
+#endif
+}
+
+// Pass-A threads per workgroup for N = 2^16 (2^13-cell segments, 32 cells
+// each); N = 2^15 uses 256.
+constexpr int kTpBlock13 = 512;
+
+// Persistent pass A: the workgroup takes tiles first, first + stride, ..
+// (tiles of transforms past the batch are skipped).  stride is a multiple of
+// 32, so every tile of the workgroup has the same segment j, passed as a
+// constant (each j gets its own code with only the registers it needs).
+//
+// Issuing the next tile's loads during the current tile's backward rounds
+// and chain was measured and gained nothing: the gather is bound by the
+// number of cache lines each workgroup requests (all of x, for every
+// segment), not by their latency.
+template <int J, int DT, bool SWAP, int MC_LOG2, int NT, int WAVE, class Sync, class WSync,
+          typename GP, typename LP>
+QFT_HD void tp_pass_a2_loop_j(const typename Store<DT>::T* x, GP W, LP L, int64_t batch,
+                              int64_t ntiles, int64_t first, int64_t stride, const float* sec,
+                              int tid, Sync sync, WSync wsync) {
+  constexpr int MC = 1 << MC_LOG2;
+  constexpr int logn = MC_LOG2 + 3;
+  for (int64_t T = tp_next_tile(first, stride, ntiles, batch); T < ntiles;
+       T = tp_next_tile(T + stride, stride, ntiles, batch)) {
+    const int64_t t = tp_tile_transform(T);
+    // Every LDS and table address of the body derives from tid; recomputing
+    // them per tile keeps the compiler from holding hundreds of them live
+    // across the loop (which spilled).
+    launder(tid);
+    TpRaw<DT, MC / NT> r;
+    tp_load_a<DT, MC_LOG2, NT>(x + (t << logn), J, tid, r);
+    tp_fold_a<DT, SWAP, MC_LOG2, NT>(r, J, tid, sec, L);
+    tp_segment<MC_LOG2, NT, WAVE>(W + (t << logn), L, J, 4 * MC, sec, tid, sync, wsync);
+    sync();  // the segment's last LDS reads before the next tile's LDS writes
   }
-  float2 topv = make_float2(0.f, 0.f);
-  if (j == 0 && tid == 0) topv = sw<SWAP>(Store<DT>::ld(xt, h));  // c(N/2)
-#pragma unroll
-  for (int it = 0; it < NI; ++it) {
-    const int q = tid + it * NT;
-    L[q] = vc[it];
-    L[MC + q] = vs[it];
+}
+
+template <int DT, bool SWAP, int MC_LOG2, int NT, int WAVE, class Sync, class WSync,
+          typename GP, typename LP>
+QFT_HD void tp_pass_a2_loop(const typename Store<DT>::T* x, GP W, LP L, int64_t batch,
+                            int64_t ntiles, int64_t first, int64_t stride, const float* sec,
+                            int tid, Sync sync, WSync wsync) {
+  switch (tp_tile_segment(first)) {
+    case 0:
+      tp_pass_a2_loop_j<0, DT, SWAP, MC_LOG2, NT, WAVE>(x, W, L, batch, ntiles, first, stride,
+                                                        sec, tid, sync, wsync);
+      break;
+    case 1:
+      tp_pass_a2_loop_j<1, DT, SWAP, MC_LOG2, NT, WAVE>(x, W, L, batch, ntiles, first, stride,
+                                                        sec, tid, sync, wsync);
+      break;
+    case 2:
+      tp_pass_a2_loop_j<2, DT, SWAP, MC_LOG2, NT, WAVE>(x, W, L, batch, ntiles, first, stride,
+                                                        sec, tid, sync, wsync);
+      break;
+    default:
+      tp_pass_a2_loop_j<3, DT, SWAP, MC_LOG2, NT, WAVE>(x, W, L, batch, ntiles, first, stride,
+                                                        sec, tid, sync, wsync);
+      break;
   }
-  if (j == 0 && tid == 0) L[2 * MC] = topv;
-  tp_segment<MC_LOG2, NT, WAVE>(wt, L, j, h, sec, tid, sync, wsync);
 }
 
 // Segment pass of the multi-pass path: workgroup j of transform heap wt

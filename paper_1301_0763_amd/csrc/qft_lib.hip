@@ -36,23 +36,19 @@
 namespace qftk {
 
 // Two-pass path, N = 8 * 2^MC_LOG2.  Pass A: both sides of one segment per
-// workgroup, 4 workgroups per transform; block b serves transform
-// 8*(b/32) + b%8 and segment (b/8)%4, so that the workgroups of a transform
-// share b%8, i.e. land on the same XCD (round-robin dispatch) and find x in
-// that XCD's L2.
+// workgroup, 4 tiles per transform (tp_tile_transform / tp_tile_segment put
+// the four on one XCD); a grid smaller than the tile count is persistent
+// and prefetches each next tile's x (tp_pass_a2_loop).
 template <int MC_LOG2, int BLOCK, int DT, bool SWAP>
 __global__ __launch_bounds__(BLOCK) void tp_a2_kernel(const typename Store<DT>::T* x, float2* W,
-                                                       int64_t batch, const float* sec) {
+                                                       int64_t batch, int64_t ntiles,
+                                                       const float* sec) {
   constexpr int MC = 1 << MC_LOG2;
-  constexpr int logn = MC_LOG2 + 3;
   __shared__ float2 Ll[padded_cells<kPad>(2 * MC + 1)];
   const PadPtr<kPad> L{Ll, 0};
-  const int64_t b = blockIdx.x;
-  const int r = (int)(b & 31);
-  const int64_t t = (b >> 5) * 8 + (r & 7);
-  if (t >= batch) return;
-  tp_pass_a2<DT, SWAP, MC_LOG2, BLOCK, kWave>(x + (t << logn), W + (t << logn), L, r >> 3, sec,
-                                              (int)threadIdx.x, DevSync{}, DevWaveSync{});
+  tp_pass_a2_loop<DT, SWAP, MC_LOG2, BLOCK, kWave>(x, W, L, batch, ntiles, (int64_t)blockIdx.x,
+                                                   (int64_t)gridDim.x, sec, (int)threadIdx.x,
+                                                   DevSync{}, DevWaveSync{});
 }
 
 template <int MC_LOG2, int DT, bool SWAP>
@@ -85,10 +81,12 @@ struct LargeItem {
   int64_t batch;
 };
 
-// A schedule: tile-group launches, in order, for the transforms of N <= 2^14.
+// A schedule: tile-group launches, in order, for the transforms of N <= 2^14,
+// and how pass A of the two-pass path (N = 2^15, 2^16) covers its tiles.
 struct Schedule {
   std::string name;
   std::vector<qftk::TileGroup> groups;
+  bool tp_persistent = true;  // resident grid with prefetch, else one workgroup per tile
 };
 
 }  // namespace
@@ -107,8 +105,10 @@ struct qft_plan_s {
   int max_log2n = 0;
   int cus = 0;
   float* d_sec = nullptr;
-  float2* d_work = nullptr;  // 2 buffers for the two-pass / multi-pass paths
+  float2* d_work = nullptr;  // heap buffers of the two-pass / multi-pass paths
   int64_t work_cells = 0;    // cells per buffer
+  int work_buffers = 0;      // 1 (two-pass only) or 2 (multi-pass)
+  int64_t tp_resident[2] = {0, 0};  // pass-A workgroups resident at once, N = 2^15, 2^16
   std::vector<Schedule> schedules;
   int chosen = 0;
   std::vector<LargeItem> large;  // common to every schedule
@@ -179,7 +179,7 @@ qft_status alloc_common(qft_plan_s* p) {
   QFT_HIP(hipMalloc(&p->d_sec, nt * sizeof(float)));
   QFT_HIP(hipMemcpy(p->d_sec, h.data(), nt * sizeof(float), hipMemcpyHostToDevice));
   if (p->work_cells > 0) {
-    hipError_t e = hipMalloc(&p->d_work, 2 * p->work_cells * sizeof(float2));
+    hipError_t e = hipMalloc(&p->d_work, p->work_buffers * p->work_cells * sizeof(float2));
     if (e != hipSuccess) {
       g_last_hip_error = (int)e;
       return QFT_ERROR_ALLOC;
@@ -236,23 +236,28 @@ inline unsigned grid_for(int64_t work, int block) {
 }
 
 // Two-pass path (N = 2^15, 2^16): pass A into the heap buffer W, pass B to X.
+// `resident` is the number of pass-A workgroups the device holds at once
+// (0: one workgroup per tile, no persistence).
 template <int DT, bool SWAP>
 qft_status launch_twopass(const void* in, void* out, int log2n, int64_t batch, const float* sec,
-                          float2* W, hipStream_t st) {
+                          float2* W, int64_t resident, hipStream_t st) {
   using T = typename qftk::Store<DT>::T;
   const T* x = (const T*)in;
   T* X = (T*)out;
-  const int64_t blocks_a = ((batch + 7) / 8) * 64;
-  if (blocks_a > 0x7fffffff) return QFT_ERROR_INVALID_VALUE;
+  const int64_t ntiles = ((batch + 7) / 8) * 32;
+  if (ntiles > 0x7fffffff) return QFT_ERROR_INVALID_VALUE;
+  int64_t grid_a = ntiles;
+  if (resident > 0 && resident < ntiles)  // persistent; whole groups of 32 keep j per workgroup
+    grid_a = resident >= 32 ? resident / 32 * 32 : resident;
   const unsigned gb = grid_for(batch << (log2n - 3), 256);
   if (log2n == 16) {
-    hipLaunchKernelGGL((qftk::tp_a2_kernel<13, 512, DT, SWAP>), dim3((unsigned)(blocks_a / 2)),
-                       dim3(512), 0, st, x, W, batch, sec);
+    hipLaunchKernelGGL((qftk::tp_a2_kernel<13, qftk::kTpBlock13, DT, SWAP>), dim3((unsigned)grid_a),
+                       dim3(qftk::kTpBlock13), 0, st, x, W, batch, ntiles, sec);
     hipLaunchKernelGGL((qftk::tp_b_kernel<13, DT, SWAP>), dim3(gb), dim3(256), 0, st,
                        (const float2*)W, X, batch);
   } else {
-    hipLaunchKernelGGL((qftk::tp_a2_kernel<12, 256, DT, SWAP>), dim3((unsigned)(blocks_a / 2)),
-                       dim3(256), 0, st, x, W, batch, sec);
+    hipLaunchKernelGGL((qftk::tp_a2_kernel<12, 256, DT, SWAP>), dim3((unsigned)grid_a),
+                       dim3(256), 0, st, x, W, batch, ntiles, sec);
     hipLaunchKernelGGL((qftk::tp_b_kernel<12, DT, SWAP>), dim3(gb), dim3(256), 0, st,
                        (const float2*)W, X, batch);
   }
@@ -262,10 +267,12 @@ qft_status launch_twopass(const void* in, void* out, int log2n, int64_t batch, c
 
 // Transforms longer than one workgroup's LDS.
 template <int DT, bool SWAP>
-qft_status launch_large(const void* in, void* out, int log2n, int64_t batch, const float* sec,
-                        float2* W0, float2* W1, hipStream_t st) {
+qft_status launch_large(const qft_plan_s* p, const Schedule& s, const void* in, void* out,
+                        int log2n, int64_t batch, float2* W0, float2* W1, hipStream_t st) {
+  const float* sec = p->d_sec;
   if (log2n == 15 || log2n == 16)
-    return launch_twopass<DT, SWAP>(in, out, log2n, batch, sec, W0, st);
+    return launch_twopass<DT, SWAP>(in, out, log2n, batch, sec, W0,
+                                    s.tp_persistent ? p->tp_resident[log2n - 15] : 0, st);
   const hipError_t e = qftk::launch_multipass<DT>(SWAP, in, out, log2n, batch, sec, W0, W1, st);
   return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
 }
@@ -288,10 +295,11 @@ qft_status run_schedule(const qft_plan_s* p, const Schedule& s, const void* in, 
     if (e != hipSuccess) return hip_fail(e);
   }
   float2* W0 = p->d_work;
-  float2* W1 = p->d_work + p->work_cells;
+  float2* W1 = p->work_buffers > 1 ? p->d_work + p->work_cells : nullptr;
   for (const LargeItem& it : p->large) {
-    const qft_status r = launch_large<DT, SWAP>((const E*)in + it.offset, (E*)out + it.offset,
-                                                it.log2n, it.batch, p->d_sec, W0, W1, st);
+    const qft_status r = launch_large<DT, SWAP>(p, s, (const E*)in + it.offset,
+                                                (E*)out + it.offset, it.log2n, it.batch, W0, W1,
+                                                st);
     if (r != QFT_SUCCESS) return r;
   }
   return QFT_SUCCESS;
@@ -359,6 +367,30 @@ qft_status run_real(const qft_plan_s* p, int kind, const qftk::RealArgs& a, hipS
     default: break;
   }
   return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
+}
+
+// Pass-A workgroups the device holds at once (resident grid of the
+// persistent two-pass launch); 0 if the occupancy query fails, which makes
+// the launch fall back to one workgroup per tile.
+template <int DT>
+void set_tp_resident_dt(qft_plan_s* p) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, reinterpret_cast<const void*>(&qftk::tp_a2_kernel<12, 256, DT, false>), 256, 0) ==
+          hipSuccess && nb > 0)
+    p->tp_resident[0] = (int64_t)nb * p->cus;
+  nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, reinterpret_cast<const void*>(&qftk::tp_a2_kernel<13, qftk::kTpBlock13, DT, false>),
+          qftk::kTpBlock13, 0) ==
+          hipSuccess && nb > 0)
+    p->tp_resident[1] = (int64_t)nb * p->cus;
+  (void)hipGetLastError();
+}
+
+void set_tp_resident(qft_plan_s* p) {
+  if (p->dtype == QFT_C16) set_tp_resident_dt<1>(p);
+  else set_tp_resident_dt<0>(p);
 }
 
 qft_plan_s* new_plan(int device, qft_dtype dtype, int cus) {
@@ -429,8 +461,15 @@ qft_status qft_plan_create(qft_plan_t* plan, int log2n, int64_t batch, qft_dtype
     if (s == QFT_SUCCESS) p->schedules.push_back(sc);
   } else {
     p->work_cells = batch << log2n;
+    p->work_buffers = log2n <= 16 ? 1 : 2;
     p->large.push_back({log2n, 0, batch});
-    p->schedules.push_back(Schedule{log2n <= 16 ? "two-pass" : "multi-pass", {}});
+    if (log2n <= 16) {
+      p->schedules.push_back(Schedule{"two-pass", {}, true});
+      p->schedules.push_back(Schedule{"two-pass/all", {}, false});
+    } else {
+      p->schedules.push_back(Schedule{"multi-pass", {}, true});
+    }
+    set_tp_resident(p);
   }
   if (s == QFT_SUCCESS) s = alloc_common(p);
   if (s != QFT_SUCCESS) {
@@ -479,7 +518,9 @@ qft_status qft_plan_create_uneven(qft_plan_t* plan, const int32_t* log2n, int64_
   for (int64_t i : big) {
     p->large.push_back({log2n[i], off[i], 1});
     p->work_cells = std::max<int64_t>(p->work_cells, (int64_t)1 << log2n[i]);
+    p->work_buffers = std::max(p->work_buffers, log2n[i] <= 16 ? 1 : 2);
   }
+  if (!big.empty()) set_tp_resident(p);
   // Candidate schedules: tile size for N <= 2^10, 2^11, 2^12, 2^13 and 2^14;
   // sizes with the same tile size share one launch.  Each comes with a
   // resident (persistent) grid and, as "<name>/all", with one workgroup per
@@ -661,7 +702,8 @@ qft_status qft_plan_create_real(qft_plan_t* plan, int log2n, int64_t batch, qft_
   if (log2n > qftk::kMaxTileLog2) {
     // multi-pass path on the transform slots, heap buffers of slots * N cells
     p->work_cells = slots << log2n;
-    p->schedules.push_back(Schedule{"multi-pass/real", {}});
+    p->work_buffers = 2;
+    p->schedules.push_back(Schedule{"multi-pass/real", {}, true});
   } else {
     const int tl = std::max(qftk::kMinTileLog2, log2n);
     const int64_t per = (int64_t)1 << (tl - log2n);

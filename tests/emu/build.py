@@ -33,7 +33,7 @@ def load():
     i, vp, i64 = ctypes.c_int, ctypes.c_void_p, ctypes.c_int64
     L.emu_multipass.argtypes = [i, i, vp, vp, i, i64, i, i]
     L.emu_uneven.argtypes = [i, i, vp, vp, ctypes.POINTER(ctypes.c_int32), i64, i, i]
-    L.emu_twopass.argtypes = [i, i, vp, vp, i, i64]
+    L.emu_twopass.argtypes = [i, i, vp, vp, i, i64, i64]
     L.emu_tile_s.argtypes = [i, i, vp, vp, i, i, vp]
     L.emu_tile_real.argtypes = [i, i, i, i64, vp, vp, vp, vp]
     L.emu_multipass_real.argtypes = [i, i, i, i64, vp, vp, vp, vp, i, i]

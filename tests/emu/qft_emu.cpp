@@ -526,12 +526,13 @@ int uneven_impl(const void* x, void* X, const int32_t* log2n, int64_t count, int
 }
 
 template <int DT, bool SWAP, int MC_LOG2>
-int twopass_mc(const void* x, void* X, int64_t batch) {
+int twopass_mc(const void* x, void* X, int64_t batch, int64_t grid) {
   using E = typename qftk::Store<DT>::T;
   constexpr int MC = 1 << MC_LOG2;
-  // threads per workgroup: the GPU's (32 cells per thread: 256 for 2^12-cell
-  // segments, 512 for 2^13), else <= 32
-  constexpr int NT = MC_LOG2 >= 12 ? (2 * MC) / 32 : (MC < 32 ? MC : 32);
+  // threads per workgroup: the GPU's (256 for 2^12-cell segments,
+  // kTpBlock13 for 2^13), else <= 32
+  constexpr int NT = MC_LOG2 == 13 ? qftk::kTpBlock13
+                                   : MC_LOG2 >= 12 ? (2 * MC) / 32 : (MC < 32 ? MC : 32);
   constexpr int logn = MC_LOG2 + 3;
   const int64_t cells = batch << logn;
   std::vector<float> sec = secants(logn);
@@ -542,7 +543,25 @@ int twopass_mc(const void* x, void* X, int64_t batch) {
   // write one cell)
   Tracker atr(NT);
   TPtr A{heap.data(), 0, &atr, cells};
-  for (int64_t t = 0; t < batch; ++t) {
+  if (grid > 0) {
+    // persistent launch: workgroup b takes tiles b, b + grid, .. with the
+    // next tile's loads in flight during the current one (grid % 32 == 0)
+    const int64_t ntiles = ((batch + 7) / 8) * 32;
+    for (int64_t b = 0; b < grid; ++b) {
+      const int64_t lc = 2 * MC + 1;
+      std::vector<float2> lds(lc + (lc >> kEmuPad));
+      Tracker ltr(NT);
+      TPtr L{lds.data(), 0, &ltr, lc, kEmuPad};
+      run_workgroup(NT, ltr, [&](int tid, auto sync, auto wsync) {
+        tl_actor = b * NT + tid;
+        qftk::tp_pass_a2_loop<DT, SWAP, MC_LOG2, NT, 64>((const E*)x, A, L, batch, ntiles, b,
+                                                         grid, sec.data(), tid, sync, wsync);
+      });
+      if (ltr.oob) return -102;
+      races += ltr.races;
+    }
+  }
+  for (int64_t t = 0; t < batch && grid == 0; ++t) {
     for (int j = 0; j < 4; ++j) {
       const int64_t lc = 2 * MC + 1;
       std::vector<float2> lds(lc + (lc >> kEmuPad));
@@ -577,15 +596,15 @@ int twopass_mc(const void* x, void* X, int64_t batch) {
 }
 
 template <int DT, bool SWAP>
-int twopass_impl(const void* x, void* X, int mc_log2, int64_t batch) {
+int twopass_impl(const void* x, void* X, int mc_log2, int64_t batch, int64_t grid) {
   switch (mc_log2) {
-    case 3: return twopass_mc<DT, SWAP, 3>(x, X, batch);
-    case 4: return twopass_mc<DT, SWAP, 4>(x, X, batch);
-    case 5: return twopass_mc<DT, SWAP, 5>(x, X, batch);
-    case 7: return twopass_mc<DT, SWAP, 7>(x, X, batch);
-    case 10: return twopass_mc<DT, SWAP, 10>(x, X, batch);
-    case 12: return twopass_mc<DT, SWAP, 12>(x, X, batch);
-    case 13: return twopass_mc<DT, SWAP, 13>(x, X, batch);
+    case 3: return twopass_mc<DT, SWAP, 3>(x, X, batch, grid);
+    case 4: return twopass_mc<DT, SWAP, 4>(x, X, batch, grid);
+    case 5: return twopass_mc<DT, SWAP, 5>(x, X, batch, grid);
+    case 7: return twopass_mc<DT, SWAP, 7>(x, X, batch, grid);
+    case 10: return twopass_mc<DT, SWAP, 10>(x, X, batch, grid);
+    case 12: return twopass_mc<DT, SWAP, 12>(x, X, batch, grid);
+    case 13: return twopass_mc<DT, SWAP, 13>(x, X, batch, grid);
     default: return -5;
   }
 }
@@ -595,12 +614,15 @@ int twopass_impl(const void* x, void* X, int mc_log2, int64_t batch) {
 extern "C" {
 
 // Two-pass path with segments of 2^mc_log2 cells (N = 8 * 2^mc_log2).
-int emu_twopass(int dt, int swap, const void* x, void* X, int mc_log2, int64_t batch) {
-  if (batch < 1) return -1;
-  if (dt == 0) return swap ? twopass_impl<0, true>(x, X, mc_log2, batch)
-                           : twopass_impl<0, false>(x, X, mc_log2, batch);
-  return swap ? twopass_impl<1, true>(x, X, mc_log2, batch)
-              : twopass_impl<1, false>(x, X, mc_log2, batch);
+// grid = 0: one workgroup per tile of pass A; else a persistent grid of that
+// many workgroups (a multiple of 32, as the library launches it).
+int emu_twopass(int dt, int swap, const void* x, void* X, int mc_log2, int64_t batch,
+                int64_t grid) {
+  if (batch < 1 || grid < 0 || grid % 32 != 0) return -1;
+  if (dt == 0) return swap ? twopass_impl<0, true>(x, X, mc_log2, batch, grid)
+                           : twopass_impl<0, false>(x, X, mc_log2, batch, grid);
+  return swap ? twopass_impl<1, true>(x, X, mc_log2, batch, grid)
+              : twopass_impl<1, false>(x, X, mc_log2, batch, grid);
 }
 
 

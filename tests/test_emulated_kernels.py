@@ -126,10 +126,11 @@ def test_uneven_worklist(emu):
         off += N
 
 
-def run_tp(emu, x, mc_log2, swap=0):
+def run_tp(emu, x, mc_log2, swap=0, grid=0):
     xf = _as_c64(x)
     out = np.zeros_like(xf)
-    races = emu.emu_twopass(0, swap, xf.ctypes.data, out.ctypes.data, mc_log2, xf.shape[0])
+    races = emu.emu_twopass(0, swap, xf.ctypes.data, out.ctypes.data, mc_log2, xf.shape[0],
+                            grid)
     assert races >= 0, races
     return races, out
 
@@ -150,15 +151,33 @@ def test_two_pass_small(emu, mc_log2, swap):
     assert D.relative_l2(out, _ref(x, swap=bool(swap))).max() <= _tol(logn)
 
 
+@pytest.mark.parametrize("mc_log2,batch", [(3, 19), (5, 11), (7, 9), (10, 17)])
+@pytest.mark.parametrize("grid", [32, 64])
+def test_two_pass_persistent(emu, mc_log2, batch, grid):
+    """Persistent pass A (a grid of whole groups of 32 workgroups, each taking
+    every grid-th tile and loading the next tile's x while the current one
+    runs): bit-identical to one workgroup per tile, on batches whose last
+    group of eight transforms is ragged, and race free."""
+    logn = mc_log2 + 3
+    x = workloads.normal(600 + mc_log2, (batch, 1 << logn))
+    r0, ref = run_tp(emu, x, mc_log2)
+    r1, out = run_tp(emu, x, mc_log2, grid=grid)
+    assert r0 == 0 and r1 == 0
+    assert np.array_equal(out, ref)
+    assert D.relative_l2(out, _ref(x)).max() <= _tol(logn)
+
+
 @pytest.mark.slow
 def test_two_pass_library_size(emu):
-    """N = 2^15 and 2^16 with the library's 2^12- and 2^13-cell segments
-    (256 and 512 threads of 32 cells, as launched)."""
+    """N = 2^15 and 2^16 with the library's 2^12- and 2^13-cell segments and
+    thread counts, one workgroup per tile and persistent."""
     for mc in (12, 13):
-        x = workloads.normal(15, (1, 8 << mc))
+        x = workloads.normal(15, (9, 8 << mc))
         races, out = run_tp(emu, x, mc)
         assert races == 0
         assert D.relative_l2(out, _ref(x)).max() <= _tol(mc + 3)
+        races, pout = run_tp(emu, x, mc, grid=32)
+        assert races == 0 and np.array_equal(pout, out)
 
 
 @pytest.mark.parametrize("logn", range(1, 15))
