@@ -52,7 +52,8 @@ typedef enum {
     QFT_ERROR_OVERLAP = 4,       /* in/out partially overlap */
     QFT_ERROR_ALLOC = 5,         /* device or host allocation failed */
     QFT_ERROR_HIP = 6,           /* a HIP runtime call failed: qft_last_hip_error() */
-    QFT_ERROR_UNSUPPORTED = 7    /* device is not gfx950 / feature not built */
+    QFT_ERROR_UNSUPPORTED = 7,   /* device is not gfx950 / feature not built */
+    QFT_ERROR_SCRATCH = 8        /* qft_exec_fwd_static: beyond its static scratch */
 } qft_status;
 
 typedef enum {
@@ -89,6 +90,27 @@ qft_status qft_plan_create_uneven(qft_plan_t* plan, const int32_t* log2n, int64_
 
 /* X = F x: forward transform of every signal of the plan (eq. qft_0A). */
 qft_status qft_exec_fwd(qft_plan_t plan, const void* in, void* out, void* stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): X = F x for
+ * `batch` transforms of N = 2^log2n points, with no plan and no allocation.
+ * The same kernels as qft_exec_fwd on a uniform plan run on device pointers
+ * `in`/`out` of the CURRENT device (layout, dtype, in == out and the error
+ * codes as there).  Instead of a plan's memory they use a static scratch
+ * array of 64 MiB per GPU (a device symbol of the library, held until the
+ * process ends): the constant table, recomputed on `stream` by every call,
+ * and for log2n = 15, 16 the two-pass heap buffer.  Limits: log2n <= 16, and
+ * batch * 2^log2n <= 2^23 - 2^14 points for log2n = 15, 16; larger requests
+ * return QFT_ERROR_SCRATCH.  Every call on one GPU uses that GPU's single
+ * copy, so calls that overlap in time on one GPU (other streams, other host
+ * threads) race on it; the scratch needs no clearing (every cell a call reads
+ * is written by that call first).  The first call on each device looks up
+ * the scratch's device address and the resident grid (runtime queries, no
+ * stream work); make that call before capturing a graph.
+ */
+qft_status qft_exec_fwd_static(int log2n, int64_t batch, qft_dtype dtype, const void* in,
+                               void* out, void* stream);
 
 /*
  * x = F^H X: the adjoint (conjugate transpose), exp(+2*pi*i*n*k/N), also

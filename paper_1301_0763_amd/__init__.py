@@ -20,7 +20,8 @@ import threading
 
 from . import _lib
 from ._lib import (QFT_C16, QFT_C32, QFT_MAX_LOG2N, QFTError, qft_exec_bwd,
-                   qft_exec_dct0_dst0, qft_exec_fwd, qft_exec_rdft, qft_last_hip_error,
+                   qft_exec_dct0_dst0, qft_exec_fwd, qft_exec_fwd_static, qft_exec_rdft,
+                   qft_last_hip_error,
                    qft_plan_autotune, qft_plan_create, qft_plan_create_real,
                    qft_plan_create_uneven, qft_plan_destroy, qft_plan_info,
                    qft_plan_schedule_name, qft_plan_schedules, qft_plan_set_schedule,
@@ -32,7 +33,7 @@ __all__ = [
     "qft_plan_destroy", "qft_plan_info", "qft_secant_table", "qft_status_string",
     "qft_last_hip_error", "qft_plan_schedules", "qft_plan_schedule_name",
     "qft_plan_set_schedule", "qft_plan_autotune", "qft_plan_create_real", "qft_exec_rdft",
-    "qft_exec_dct0_dst0", "RealPlan", "rdft", "dct0", "dst0",
+    "qft_exec_dct0_dst0", "qft_exec_fwd_static", "RealPlan", "rdft", "dct0", "dst0",
     "QFT_C32", "QFT_C16", "QFT_MAX_LOG2N",
 ]
 

@@ -17,6 +17,7 @@ QFT_ERROR_OVERLAP = 4
 QFT_ERROR_ALLOC = 5
 QFT_ERROR_HIP = 6
 QFT_ERROR_UNSUPPORTED = 7
+QFT_ERROR_SCRATCH = 8
 
 QFT_C32 = 0
 QFT_C16 = 1
@@ -66,11 +67,12 @@ def lib():
         L.qft_plan_create_real.argtypes = [ctypes.POINTER(vp), i32, i64, i32, i32]
         L.qft_exec_rdft.argtypes = [vp, vp, vp, vp]
         L.qft_exec_dct0_dst0.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.qft_exec_fwd_static.argtypes = [i32, i64, i32, vp, vp, vp]
         for f in ("qft_plan_create", "qft_plan_create_uneven", "qft_exec_fwd", "qft_exec_bwd",
                   "qft_plan_destroy", "qft_plan_info", "qft_secant_table",
                   "qft_last_hip_error", "qft_plan_schedules", "qft_plan_set_schedule",
                   "qft_plan_autotune", "qft_plan_create_real", "qft_exec_rdft",
-                  "qft_exec_dct0_dst0"):
+                  "qft_exec_dct0_dst0", "qft_exec_fwd_static"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -107,6 +109,13 @@ def qft_plan_create_uneven(log2n_list, dtype=QFT_C32, device=0):
 
 def qft_exec_fwd(plan, in_ptr, out_ptr, stream=0):
     _check(lib().qft_exec_fwd(plan, in_ptr, out_ptr, stream), "qft_exec_fwd")
+
+
+def qft_exec_fwd_static(log2n, batch, dtype, in_ptr, out_ptr, stream=0):
+    """Plan-free forward transform on the current device using the library's
+    static scratch (no device allocation; see include/qft.h)."""
+    _check(lib().qft_exec_fwd_static(int(log2n), int(batch), int(dtype), in_ptr, out_ptr,
+                                     stream), "qft_exec_fwd_static")
 
 
 def qft_exec_bwd(plan, in_ptr, out_ptr, stream=0):

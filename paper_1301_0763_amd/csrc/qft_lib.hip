@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -62,6 +63,30 @@ __global__ __launch_bounds__(256) void tp_b_kernel(const float2* W, typename Sto
     const int k = (int)(i & ((1 << (logn - 3)) - 1));
     tp_pass_b<DT, SWAP, MC_LOG2>(W + (t << logn), X + (t << logn), k);
   }
+}
+
+// Static scratch of qft_exec_fwd_static (no allocation): the constant table
+// of transforms up to 2^kStaticMaxLog2 (kStaticTabCells cells hold its
+// floats) followed by the two-pass heap buffer.  One copy per GPU, held until
+// the process ends.
+constexpr int kStaticMaxLog2 = 16;
+constexpr int64_t kStaticTabCells = ((int64_t)1 << kStaticMaxLog2) / 8;  // 2^14 floats
+constexpr int64_t kStaticCells = (int64_t)8 << 20;                      // 64 MiB
+__device__ __align__(256) float2 scratch[kStaticCells];
+
+// Constant table entries [0, nt) computed on the device in FP64 by the same
+// expression as fill_secants, rounded once to FP32.
+__global__ __launch_bounds__(256) void static_secants_kernel(float* tab, int nt) {
+  const int i = (int)(blockIdx.x * 256 + threadIdx.x);
+  if (i >= nt) return;
+  if (i == 0) {
+    tab[0] = 0.0f;
+    return;
+  }
+  const int L = 1 << (31 - __clz(i));
+  const int m = i - L;
+  const double a = M_PI * (double)(2 * L - 2 * m - 1) / (double)(4 * L);
+  tab[i] = (float)(1.0 / (2.0 * sin(a)));
 }
 
 }  // namespace qftk
@@ -403,6 +428,72 @@ qft_plan_s* new_plan(int device, qft_dtype dtype, int cus) {
   return p;
 }
 
+// Per-device state of qft_exec_fwd_static: the address of that device's copy
+// of qftk::scratch (hipGetSymbolAddress; the symbol's own name is a host
+// stand-in that must never reach a kernel) and the resident pass-A grids.
+struct StaticDev {
+  std::once_flag once;
+  hipError_t err = hipSuccess;
+  float2* ptr = nullptr;
+  int64_t tp_resident[2] = {0, 0};
+};
+constexpr int kMaxDevices = 64;
+StaticDev g_static[kMaxDevices];
+
+qft_status static_setup(int dev, StaticDev** out) {
+  if (dev < 0 || dev >= kMaxDevices) return QFT_ERROR_UNSUPPORTED;
+  StaticDev& d = g_static[dev];
+  std::call_once(d.once, [&d, dev]() {
+    d.err = hipGetSymbolAddress((void**)&d.ptr, HIP_SYMBOL(qftk::scratch));
+    if (d.err != hipSuccess) {
+      d.ptr = nullptr;
+      return;
+    }
+    qft_plan_s probe;  // plan fields the occupancy query reads, no allocation
+    probe.device = dev;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
+      probe.cus = cus;
+      set_tp_resident(&probe);
+      d.tp_resident[0] = probe.tp_resident[0];
+      d.tp_resident[1] = probe.tp_resident[1];
+    }
+    (void)hipGetLastError();
+  });
+  if (d.err != hipSuccess || !d.ptr) return hip_fail(d.err != hipSuccess ? d.err
+                                                                         : hipErrorInvalidSymbol);
+  *out = &d;
+  return QFT_SUCCESS;
+}
+
+template <int DT>
+qft_status static_exec(const StaticDev& d, int log2n, int64_t batch, const void* in, void* out,
+                       hipStream_t st) {
+  float* tab = reinterpret_cast<float*>(d.ptr);
+  const int nt = (1 << std::max(log2n, 3)) / 4;
+  hipLaunchKernelGGL(qftk::static_secants_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256),
+                     0, st, tab, nt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e);
+  if (log2n <= qftk::kMaxTileLog2) {
+    const int tl = std::max(qftk::kMinTileLog2, log2n);
+    const int64_t per = (int64_t)1 << (tl - log2n);
+    const int64_t ntiles = (batch + per - 1) / per;
+    if (ntiles > 0x7fffffff) return QFT_ERROR_INVALID_VALUE;
+    const qftk::TileGroup g{tl, (int)ntiles, (int)ntiles, nullptr, nullptr, log2n, batch, 0};
+    switch (tl) {
+      case 10: e = qftk::launch_tiles<DT, 10, false>(g, in, out, tab, st); break;
+      case 11: e = qftk::launch_tiles<DT, 11, false>(g, in, out, tab, st); break;
+      case 12: e = qftk::launch_tiles<DT, 12, false>(g, in, out, tab, st); break;
+      case 13: e = qftk::launch_tiles<DT, 13, false>(g, in, out, tab, st); break;
+      default: e = qftk::launch_tiles<DT, 14, false>(g, in, out, tab, st); break;
+    }
+    return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
+  }
+  return launch_twopass<DT, false>(in, out, log2n, batch, tab, d.ptr + qftk::kStaticTabCells,
+                                   d.tp_resident[log2n - 15], st);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -420,6 +511,9 @@ const char* qft_status_string(qft_status s) {
     case QFT_ERROR_ALLOC: return "allocation failed";
     case QFT_ERROR_HIP: return "HIP runtime error";
     case QFT_ERROR_UNSUPPORTED: return "unsupported device or feature";
+    case QFT_ERROR_SCRATCH:
+      return "request exceeds the static scratch of qft_exec_fwd_static "
+             "(log2n <= 16; batch * 2^log2n <= 8M - 16K points for log2n = 15, 16)";
   }
   return "unknown status";
 }
@@ -584,6 +678,31 @@ qft_status qft_plan_create_uneven(qft_plan_t* plan, const int32_t* log2n, int64_
 
 qft_status qft_exec_fwd(qft_plan_t plan, const void* in, void* out, void* stream) {
   return exec_impl<false>(plan, in, out, stream);
+}
+
+qft_status qft_exec_fwd_static(int log2n, int64_t batch, qft_dtype dtype, const void* in,
+                               void* out, void* stream) {
+  if (!in || !out || batch <= 0 || (dtype != QFT_C32 && dtype != QFT_C16))
+    return QFT_ERROR_INVALID_VALUE;
+  if (log2n < 1 || log2n > QFT_MAX_LOG2N) return QFT_ERROR_INVALID_SIZE;
+  if (log2n > qftk::kStaticMaxLog2) return QFT_ERROR_SCRATCH;
+  if (log2n > qftk::kMaxTileLog2 &&
+      batch > (qftk::kStaticCells - qftk::kStaticTabCells) >> log2n)
+    return QFT_ERROR_SCRATCH;
+  if (batch > ((int64_t)1 << 40) >> log2n) return QFT_ERROR_INVALID_VALUE;
+  const int64_t esz = dtype == QFT_C32 ? 8 : 4;
+  if (((uintptr_t)in % esz) != 0 || ((uintptr_t)out % esz) != 0) return QFT_ERROR_ALIGNMENT;
+  const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+  const uintptr_t bytes = (uintptr_t)((batch << log2n) * esz);
+  if (a != b && a < b + bytes && b < a + bytes) return QFT_ERROR_OVERLAP;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  StaticDev* d = nullptr;
+  const qft_status st = static_setup(dev, &d);
+  if (st != QFT_SUCCESS) return st;
+  return dtype == QFT_C32 ? static_exec<0>(*d, log2n, batch, in, out, (hipStream_t)stream)
+                          : static_exec<1>(*d, log2n, batch, in, out, (hipStream_t)stream);
 }
 
 qft_status qft_exec_bwd(qft_plan_t plan, const void* in, void* out, void* stream) {

@@ -43,8 +43,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_status_strings():
-    for s in range(0, 8):
+    for s in range(0, 9):
         assert qft.qft_status_string(s)
+    assert "static scratch" in qft.qft_status_string(_lib.QFT_ERROR_SCRATCH)
     assert "size" in qft.qft_status_string(_lib.QFT_ERROR_INVALID_SIZE)
 
 
@@ -83,6 +84,24 @@ def test_uneven_rejects():
         _lib.QFT_ERROR_INVALID_VALUE
     assert L.qft_plan_create_uneven(ctypes.byref(h), arr, 0, 0, 0) == \
         _lib.QFT_ERROR_INVALID_VALUE
+
+
+def test_static_exec_rejects_before_any_hip_call():
+    """qft_exec_fwd_static validates its arguments first (fake pointers are
+    never touched): sizes beyond the static scratch give QFT_ERROR_SCRATCH."""
+    L = _lib.lib()
+    f = L.qft_exec_fwd_static
+    p, q = 1 << 20, 1 << 40
+    assert f(10, 4, 0, None, q, None) == _lib.QFT_ERROR_INVALID_VALUE
+    assert f(10, 0, 0, p, q, None) == _lib.QFT_ERROR_INVALID_VALUE
+    assert f(10, 4, 5, p, q, None) == _lib.QFT_ERROR_INVALID_VALUE
+    assert f(0, 4, 0, p, q, None) == _lib.QFT_ERROR_INVALID_SIZE
+    assert f(25, 1, 0, p, q, None) == _lib.QFT_ERROR_INVALID_SIZE
+    assert f(17, 1, 0, p, q, None) == _lib.QFT_ERROR_SCRATCH
+    assert f(16, 128, 0, p, q, None) == _lib.QFT_ERROR_SCRATCH   # 2^23 > 2^23 - 2^14
+    assert f(15, 256, 1, p, q, None) == _lib.QFT_ERROR_SCRATCH
+    assert f(16, 4, 0, p + 4, q, None) == _lib.QFT_ERROR_ALIGNMENT
+    assert f(16, 4, 0, p, p + 64, None) == _lib.QFT_ERROR_OVERLAP
 
 
 def test_exec_and_info_reject_null_plan():
