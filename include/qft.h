@@ -67,8 +67,9 @@ typedef enum {
  * Plan for `batch` transforms of length N = 2^log2n each (Sec. 2.1 problem
  * statement).  Allocates the device constant table (Sec. 6.1: N/4 constants,
  * the secants 1/(2 cos(2*pi*q/N)) of eq. qft_38A and cos(2*pi/8)) and, for N
- * beyond one workgroup's local memory, a device scratch of 2*batch*N complex
- * FP32 values.  `device` is a HIP device ordinal.  On success *plan receives
+ * beyond one workgroup's local memory, a device scratch of batch*N complex
+ * FP32 values (N = 2^15, 2^16) or 2*batch*N (N > 2^16).  `device` is a HIP
+ * device ordinal.  On success *plan receives
  * a handle owned by the caller (free with qft_plan_destroy); on failure
  * *plan is set to NULL.
  */
@@ -136,34 +137,52 @@ qft_status qft_plan_info(qft_plan_t plan, int64_t* total_points, int64_t* algo_b
                          double* flops_5nlogn, double* flops_actual);
 
 /*
- * Schedules.  A plan holds one or more schedules, each a list of persistent
- * tile-kernel launches ("groups") that says which transform sizes run with
- * which tile size: tiles of 2^12 cells (256 threads, 4 workgroups per CU),
- * 2^13 (512 threads, 2 per CU) or 2^14 (1024 threads, 1 per CU; a uniform
- * batch of N = 2^13 or 2^14 runs 256 or 512 threads, 32 cells each), and how
- * the launch covers its tiles: a resident grid whose workgroups stride over
- * the tile list (persistent), or one workgroup per tile (name suffix
- * "/all").  Uniform plans with N <= 2^14 have one schedule per tile size
- * that holds a transform and grid policy (persistent, smallest tile first,
- * is the default); uneven plans have the tile-size assignments for
- * N <= 2^12, 2^13, 2^14 of {14,14,14}, {13,13,14}, {12,14,14}, {12,13,14}
- * (duplicates removed), each persistent and "/all"; schedule 0, the default,
- * runs every transform of up to 2^14 points in one persistent launch.  All
- * schedules compute the same result, bit for bit.
+ * Schedules.  A plan holds one or more schedules: ways to run the same
+ * computation that differ only in how the work is cut into launches and
+ * passes (every schedule of a plan gives bit-identical results).
+ *  - Uniform plans, N <= 2^14: schedule 0 ("t<T>:<r>") is the kernel
+ *    specialised for N, one workgroup per tile of 2^T = 2^max(10, r) cells;
+ *    for batches of at most 2^20 transforms, "g<T>:<r>" for every T from
+ *    max(10, r) to 14 runs the size-generic persistent kernel of uneven plans
+ *    with tiles of 2^T cells over a transform list.
+ *  - Uniform plans, N = 2^15, 2^16 (two-pass): "two-pass" (pass A as a
+ *    resident grid whose workgroups stride over the tiles, the default) and
+ *    "two-pass/all" (one workgroup per tile).
+ *  - Uniform plans, N > 2^16 (multi-pass): "multi-pass:f,b,c", the most
+ *    forward rounds, backward rounds and chain levels per global pass, for
+ *    (f,b,c) in (4,5,5) (the default), (3,5,5), (4,4,5), (4,5,4), (3,4,4),
+ *    (5,5,5).
+ *  - Uneven plans: which tile size serves each transform size of up to 2^14
+ *    points, tiles of 2^10 .. 2^14 cells; the assignments for
+ *    N <= 2^10, 2^11, 2^12, 2^13, 2^14 of {14,14,14,14,14}, {13,13,13,13,14},
+ *    {12,12,12,14,14}, {12,12,12,13,14}, {10,11,12,13,14}, {10,11,12,14,14},
+ *    {10,12,12,13,14} (duplicates for the sizes present removed), sizes with
+ *    one tile size sharing one launch, each as a resident persistent grid and
+ *    as one workgroup per tile ("/all"); names read "t<T>:<r range>+..".
+ *    Schedule 0 runs every transform of up to 2^14 points in ONE persistent
+ *    launch.  Longer transforms run after them with the default two-pass or
+ *    multi-pass schedule.
+ * A new plan starts on schedule 0, or on the schedule the autotuner chose for
+ * a plan of the same shape on the same kind of device, if the schedule cache
+ * holds one: a JSON file at $QFT_SCHEDULE_CACHE ("off" disables it), else
+ * $XDG_CACHE_HOME/qft-gfx950/schedules.json, else
+ * $HOME/.cache/qft-gfx950/schedules.json.  An unreadable file or an entry
+ * that names no schedule of the plan is ignored, so the file may be deleted
+ * at any time.
  *
  * qft_plan_schedules: number of schedules and the one exec uses.
- * qft_plan_schedule_name: a static description such as "t12:6-12+t14:13-14"
- *   (tile size : range of log2n per launch), valid until the plan is
- *   destroyed; NULL for a bad plan or index.
+ * qft_plan_schedule_name: a static description (see above), valid until the
+ *   plan is destroyed; NULL for a bad plan or index.
  * qft_plan_set_schedule: selects the schedule exec uses (e.g. a stored
  *   autotuning result); QFT_ERROR_INVALID_VALUE for a bad index.
  * qft_plan_autotune: runs every schedule once to warm up and then `reps`
- *   times (1..10000), timed with HIP events on `stream`, selects the fastest
- *   and returns its index in *chosen (may be NULL); ms[i], i < ms_len, gets
- *   the mean time of schedule i in milliseconds (ms may be NULL when
- *   ms_len = 0).  It overwrites `out` with F in (in is left unchanged unless
- *   in == out), synchronises the stream and must not be called during graph
- *   capture or while another exec of the plan is in flight.
+ *   times (1..10000), timed with HIP events on `stream`, selects the fastest,
+ *   returns its index in *chosen (may be NULL) and records it in the schedule
+ *   cache (best effort); ms[i], i < ms_len, gets the mean time of schedule i
+ *   in milliseconds (ms may be NULL when ms_len = 0).  It overwrites `out`
+ *   with F in (in is left unchanged unless in == out), synchronises the
+ *   stream and must not be called during graph capture or while another exec
+ *   of the plan is in flight.
  */
 qft_status qft_plan_schedules(qft_plan_t plan, int* count, int* chosen);
 const char* qft_plan_schedule_name(qft_plan_t plan, int schedule);
@@ -233,7 +252,12 @@ qft_status qft_secant_table(float* out, int log2n_max);
 /* Static description of a status code. */
 const char* qft_status_string(qft_status s);
 
-/* The hipError_t value of the last QFT_ERROR_HIP on this thread (0 if none). */
+/*
+ * The hipError_t value of the last QFT_ERROR_HIP on this thread (0 if none).
+ * It returns the HIP runtime's own code (an int, as hipError_t is), not a
+ * qft_status: QFT_ERROR_HIP says that a HIP call failed, this says which
+ * error it reported.
+ */
 int qft_last_hip_error(void);
 
 #ifdef __cplusplus

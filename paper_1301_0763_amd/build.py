@@ -23,7 +23,8 @@ SRC = os.path.join(CSRC, "qft_lib.hip")
 TILES = os.path.join(CSRC, "qft_tiles.hip")
 MULTI = os.path.join(CSRC, "qft_multipass.hip")
 DEPS = [SRC, TILES, MULTI] + [os.path.join(CSRC, f) for f in
-                       ("qft_device.hpp", "qft_schedule.hpp", "qft_kernels.hpp")]
+                       ("qft_device.hpp", "qft_schedule.hpp", "qft_kernels.hpp",
+                        "qft_cache.hpp")]
 LIB = os.path.join(HERE, "libqft.so")
 ROOT = os.path.dirname(HERE)
 HEADER = os.path.join(ROOT, "include", "qft.h")

@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include "qft_device.hpp"
+#include "qft_schedule.hpp"
 
 namespace qftk {
 
@@ -101,7 +102,8 @@ constexpr int kMpSegLog2 = 12;  // LDS segment of the multi-pass path
 
 template <int DT>
 hipError_t launch_multipass(bool swap, const void* in, void* out, int log2n, int64_t batch,
-                            const float* sec, float2* W0, float2* W1, hipStream_t st);
+                            const float* sec, float2* W0, float2* W1, MpLevels lv,
+                            hipStream_t st);
 
 template <int DT>
 hipError_t launch_multipass_real(int kind, const RealArgs& a, int log2n, int64_t rows,

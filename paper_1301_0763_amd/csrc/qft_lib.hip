@@ -30,6 +30,7 @@
 #include <string>
 #include <vector>
 
+#include "qft_cache.hpp"
 #include "qft_kernels.hpp"
 #include "qft_schedule.hpp"
 #include "../../include/qft.h"
@@ -111,7 +112,8 @@ struct LargeItem {
 struct Schedule {
   std::string name;
   std::vector<qftk::TileGroup> groups;
-  bool tp_persistent = true;  // resident grid with prefetch, else one workgroup per tile
+  bool tp_persistent = true;  // two-pass pass A: resident grid, else one workgroup per tile
+  qftk::MpLevels mp{};        // multi-pass: most rounds / levels per global pass
 };
 
 }  // namespace
@@ -138,6 +140,8 @@ struct qft_plan_s {
   int chosen = 0;
   std::vector<LargeItem> large;  // common to every schedule
   std::vector<void*> dev_allocs;  // tile lists of the groups (shared between schedules)
+  std::string cache_key;          // schedule-cache key (device and plan shape)
+  bool from_cache = false;        // the chosen schedule came from the cache
 };
 
 namespace {
@@ -179,6 +183,38 @@ qft_status check_device(int device, int* cus) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return QFT_ERROR_UNSUPPORTED;
   *cus = prop.multiProcessorCount;
   return QFT_SUCCESS;
+}
+
+// Schedule-cache key: the device (gfx950 and its CU count) and the plan's
+// shape; uneven plans are identified by a 64-bit FNV-1a hash of their sizes.
+std::string plan_key(const qft_plan_s* p, const char* kind, const int32_t* sizes,
+                     int64_t count) {
+  std::string k = "gfx950/" + std::to_string(p->cus) + "cu/" + kind + "/" +
+                  (p->dtype == QFT_C32 ? "c32" : "c16") + "/";
+  if (sizes) {
+    uint64_t h = 1469598103934665603ull;
+    for (int64_t i = 0; i < count; ++i) {
+      h ^= (uint64_t)(uint32_t)sizes[i];
+      h *= 1099511628211ull;
+    }
+    char buf[40];
+    std::snprintf(buf, sizeof buf, "%lld:%016llx", (long long)count, (unsigned long long)h);
+    return k + buf;
+  }
+  return k + std::to_string(p->log2n) + "x" + std::to_string(p->batch);
+}
+
+// Starts the plan on the schedule the cache names for its key, if any.
+void apply_cached_schedule(qft_plan_s* p) {
+  std::string name;
+  if (!qftk::schedule_cache_lookup(qftk::schedule_cache_path(), p->cache_key, name)) return;
+  for (size_t i = 0; i < p->schedules.size(); ++i) {
+    if (p->schedules[i].name == name) {
+      p->chosen = (int)i;
+      p->from_cache = true;
+      return;
+    }
+  }
 }
 
 void add_costs(qft_plan_s* p, int log2n, int64_t count) {
@@ -298,7 +334,8 @@ qft_status launch_large(const qft_plan_s* p, const Schedule& s, const void* in, 
   if (log2n == 15 || log2n == 16)
     return launch_twopass<DT, SWAP>(in, out, log2n, batch, sec, W0,
                                     s.tp_persistent ? p->tp_resident[log2n - 15] : 0, st);
-  const hipError_t e = qftk::launch_multipass<DT>(SWAP, in, out, log2n, batch, sec, W0, W1, st);
+  const hipError_t e =
+      qftk::launch_multipass<DT>(SWAP, in, out, log2n, batch, sec, W0, W1, s.mp, st);
   return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
 }
 
@@ -546,22 +583,46 @@ qft_status qft_plan_create(qft_plan_t* plan, int log2n, int64_t batch, qft_dtype
   p->max_log2n = log2n;
   add_costs(p, log2n, batch);
   if (log2n <= qftk::kMaxTileLog2) {
-    // one workgroup per tile of 2^max(10, log2n) cells
+    // schedule 0: the kernel specialised for this size, one workgroup per
+    // tile of 2^max(10, log2n) cells
     const int tl = std::max(qftk::kMinTileLog2, log2n);
     Schedule sc;
     sc.name = "t" + std::to_string(tl) + ":" + std::to_string(log2n);
     sc.groups.resize(1);
     s = uniform_group(p, tl, &sc.groups[0]);
     if (s == QFT_SUCCESS) p->schedules.push_back(sc);
+    // the size-generic persistent kernel of uneven plans on a transform list,
+    // tiles of 2^tl2 cells for every tl2 that holds a transform (batches of
+    // at most 2^20 transforms: the list costs 8 bytes per transform)
+    if (batch <= ((int64_t)1 << 20)) {
+      std::vector<int32_t> sizes((size_t)batch, log2n);
+      std::vector<int64_t> off;
+      qftk::packed_offsets(sizes.data(), batch, off);
+      for (int tl2 = tl; tl2 <= qftk::kMaxTileLog2 && s == QFT_SUCCESS; ++tl2) {
+        Schedule g;
+        g.name = "g" + std::to_string(tl2) + ":" + std::to_string(log2n);
+        g.groups.resize(1);
+        s = uneven_group(p, sizes.data(), off, log2n, log2n, tl2, &g.groups[0]);
+        if (s == QFT_SUCCESS) p->schedules.push_back(g);
+      }
+    }
   } else {
     p->work_cells = batch << log2n;
     p->work_buffers = log2n <= 16 ? 1 : 2;
     p->large.push_back({log2n, 0, batch});
     if (log2n <= 16) {
-      p->schedules.push_back(Schedule{"two-pass", {}, true});
-      p->schedules.push_back(Schedule{"two-pass/all", {}, false});
+      p->schedules.push_back(Schedule{"two-pass", {}, true, {}});
+      p->schedules.push_back(Schedule{"two-pass/all", {}, false, {}});
     } else {
-      p->schedules.push_back(Schedule{"multi-pass", {}, true});
+      // splits of the global passes: most forward rounds / backward rounds /
+      // chain levels per pass; the first is the default
+      const int splits[][3] = {{4, 5, 5}, {3, 5, 5}, {4, 4, 5}, {4, 5, 4}, {3, 4, 4}, {5, 5, 5}};
+      for (const auto& sp : splits) {
+        Schedule m{"multi-pass:" + std::to_string(sp[0]) + "," + std::to_string(sp[1]) + "," +
+                       std::to_string(sp[2]),
+                   {}, true, qftk::MpLevels{sp[0], sp[1], sp[2]}};
+        p->schedules.push_back(m);
+      }
     }
     set_tp_resident(p);
   }
@@ -570,6 +631,8 @@ qft_status qft_plan_create(qft_plan_t* plan, int log2n, int64_t batch, qft_dtype
     free_plan(p);
     return s;
   }
+  p->cache_key = plan_key(p, "u", nullptr, 0);
+  apply_cached_schedule(p);
   *plan = p;
   return QFT_SUCCESS;
 }
@@ -672,6 +735,8 @@ qft_status qft_plan_create_uneven(qft_plan_t* plan, const int32_t* log2n, int64_
     free_plan(p);
     return s;
   }
+  p->cache_key = plan_key(p, "v", log2n, count);
+  apply_cached_schedule(p);
   *plan = p;
   return QFT_SUCCESS;
 }
@@ -788,7 +853,13 @@ qft_status qft_plan_autotune(qft_plan_t plan, const void* in, void* out, void* s
   (void)hipEventDestroy(e1);
   if (c != QFT_SUCCESS) return c;
   plan->chosen = best;
+  plan->from_cache = false;
   if (chosen) *chosen = best;
+  // remembered for later plans of this shape (best effort: a cache that
+  // cannot be written only means they tune again)
+  if (plan->schedules.size() > 1 && !plan->cache_key.empty())
+    (void)qftk::schedule_cache_store(qftk::schedule_cache_path(), plan->cache_key,
+                                     plan->schedules[best].name);
   return QFT_SUCCESS;
 }
 

@@ -94,14 +94,6 @@ namespace {
 
 constexpr int kMpSegThreads = (2 << kMpSegLog2) / 32;
 
-// Most forward rounds, backward rounds and chain levels per global pass
-// (QFT_MP_LEVELS=f,b,c overrides the defaults at build time).
-#if defined(QFT_MP_LEVELS)
-constexpr MpLevels kLevels{QFT_MP_LEVELS};
-#else
-constexpr MpLevels kLevels{};
-#endif
-
 unsigned grid_for(int64_t work) {
   int64_t g = (work + MP_BLOCK - 1) / MP_BLOCK;
   const int64_t cap = 1 << 20;
@@ -203,14 +195,18 @@ struct GpuMultipass {
   }
 };
 
+// `lv`: most forward rounds, backward rounds and chain levels per global
+// pass (1 .. 5 each; a plan's schedules offer several splits).
 template <class IO>
 hipError_t run_multipass(const IO& io, int log2n, int64_t batch, const float* sec, float2* W0,
-                         float2* W1, hipStream_t st) {
+                         float2* W1, MpLevels lv, hipStream_t st) {
   if (log2n < kMpSegLog2 + 3 || log2n > 24 || batch < 1 ||
       (batch << (log2n - 1 - kMpSegLog2)) > 0x7fffffff)
     return hipErrorInvalidValue;
+  if (lv.fwd < 1 || lv.fwd > 5 || lv.bwd < 1 || lv.bwd > 5 || lv.chain < 1 || lv.chain > 5)
+    return hipErrorInvalidValue;
   GpuMultipass<IO> ex{io, log2n, batch, sec, W0, W1, st};
-  multipass_schedule(ex, log2n, kMpSegLog2, kLevels);
+  multipass_schedule(ex, log2n, kMpSegLog2, lv);
   if (ex.err != hipSuccess) return ex.err;
   return hipGetLastError();
 }
@@ -219,13 +215,14 @@ hipError_t run_multipass(const IO& io, int log2n, int64_t batch, const float* se
 
 template <int DT>
 hipError_t launch_multipass(bool swap, const void* in, void* out, int log2n, int64_t batch,
-                            const float* sec, float2* W0, float2* W1, hipStream_t st) {
+                            const float* sec, float2* W0, float2* W1, MpLevels lv,
+                            hipStream_t st) {
   using E = typename Store<DT>::T;
   if (swap)
     return run_multipass(ContigRtIO<DT, true>((const E*)in, (E*)out, log2n), log2n, batch, sec,
-                         W0, W1, st);
+                         W0, W1, lv, st);
   return run_multipass(ContigRtIO<DT, false>((const E*)in, (E*)out, log2n), log2n, batch, sec,
-                       W0, W1, st);
+                       W0, W1, lv, st);
 }
 
 template <int DT>
@@ -236,14 +233,15 @@ hipError_t launch_multipass_real(int kind, const RealArgs& a, int log2n, int64_t
   const int64_t slots = (rows + 1) / 2;
   if (kind == 0)
     return run_multipass(RealPairIO<DT, 0>{(const R*)a.in0, (E*)a.out0, rows, log2n}, log2n,
-                         slots, sec, W0, W1, st);
+                         slots, sec, W0, W1, MpLevels{}, st);
   return run_multipass(DctDstIO<DT, 0>{(const R*)a.in0, (const R*)a.in1, (R*)a.out0,
                                        (R*)a.out1, rows, log2n},
-                       log2n, slots, sec, W0, W1, st);
+                       log2n, slots, sec, W0, W1, MpLevels{}, st);
 }
 
 template hipError_t launch_multipass<QFT_MP_DT>(bool, const void*, void*, int, int64_t,
-                                                const float*, float2*, float2*, hipStream_t);
+                                                const float*, float2*, float2*, MpLevels,
+                                                hipStream_t);
 template hipError_t launch_multipass_real<QFT_MP_DT>(int, const RealArgs&, int, int64_t,
                                                      const float*, float2*, float2*,
                                                      hipStream_t);

@@ -8,6 +8,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+# The library keeps autotuned schedules in a cache file; the tests use one of
+# their own (a fresh temporary file per session) so that a user's cache never
+# changes which schedule a test's plan starts on.
+if "QFT_SCHEDULE_CACHE" not in os.environ:
+    import tempfile
+    os.environ["QFT_SCHEDULE_CACHE"] = os.path.join(
+        tempfile.mkdtemp(prefix="qft_sched_"), "schedules.json")
+
+
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
     config.addinivalue_line("markers", "slow: long-running CPU test")

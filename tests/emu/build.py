@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 SRC = os.path.join(HERE, "qft_emu.cpp")
 LIB = os.path.join(HERE, "libqft_emu.so")
 DEPS = [SRC] + [os.path.join(ROOT, "paper_1301_0763_amd", "csrc", f)
-                for f in ("qft_device.hpp", "qft_schedule.hpp")]
+                for f in ("qft_device.hpp", "qft_schedule.hpp", "qft_cache.hpp")]
 
 
 def build(force=True):
@@ -38,8 +38,14 @@ def load():
     L.emu_tile_real.argtypes = [i, i, i, i64, vp, vp, vp, vp]
     L.emu_multipass_real.argtypes = [i, i, i, i64, vp, vp, vp, vp, i, i]
     L.emu_race_model_check.argtypes = [i, i]
+    L.emu_multipass_levels.argtypes = [i, vp, vp, i, i64, i, i, i, i, i]
+    cp = ctypes.c_char_p
+    L.emu_cache_store.argtypes = [cp, cp, cp]
+    L.emu_cache_lookup.argtypes = [cp, cp, ctypes.c_char_p, i]
+    L.emu_cache_path.argtypes = [ctypes.c_char_p, i]
     for f in (L.emu_multipass, L.emu_uneven, L.emu_twopass, L.emu_tile_s,
-              L.emu_tile_real, L.emu_multipass_real, L.emu_race_model_check):
+              L.emu_tile_real, L.emu_multipass_real, L.emu_race_model_check,
+              L.emu_multipass_levels, L.emu_cache_store, L.emu_cache_lookup, L.emu_cache_path):
         f.restype = i
     return L
 

@@ -23,6 +23,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "../../paper_1301_0763_amd/csrc/qft_cache.hpp"
 #include "../../paper_1301_0763_amd/csrc/qft_device.hpp"
 #include "../../paper_1301_0763_amd/csrc/qft_schedule.hpp"
 
@@ -457,22 +458,22 @@ struct EmuMultipass {
 
 template <class IO>
 int run_multipass(const IO& io, int logn, int64_t batch, int seg_log2, int nthr,
-                  const float* sec) {
+                  const float* sec, qftk::MpLevels lv = qftk::MpLevels{}) {
   std::vector<float2> w0((size_t)batch << logn), w1((size_t)batch << logn);
   EmuMultipass<IO> ex{io, logn, batch, seg_log2, nthr, sec, w0.data(), w1.data(),
                       (int64_t)batch << logn};
-  qftk::multipass_schedule(ex, logn, seg_log2);
+  qftk::multipass_schedule(ex, logn, seg_log2, lv);
   if (ex.races < 0 || ex.gtr.oob) return -4;
   return (int)(ex.races + ex.gtr.races);
 }
 
 template <int DT, bool SWAP>
 int multipass_impl(const void* x, void* X, int logn, int64_t batch, int seg_log2, int nthr,
-                   const float* sec) {
+                   const float* sec, qftk::MpLevels lv = qftk::MpLevels{}) {
   using E = typename qftk::Store<DT>::T;
   if (logn < seg_log2 + 3) return -3;
   return run_multipass(qftk::ContigRtIO<DT, SWAP>((const E*)x, (E*)X, logn), logn, batch,
-                       seg_log2, nthr, sec);
+                       seg_log2, nthr, sec, lv);
 }
 
 // Multi-pass path of a real-input plan (kind 0: rdft, 1: DCT-0/DST-0).
@@ -699,6 +700,41 @@ int emu_race_model_check(int order, int same_wave) {
     (void)v;
   });
   return (int)tr.races;
+}
+
+// Multi-pass path with a given split of the global passes (most forward
+// rounds, backward rounds, chain levels per pass).
+int emu_multipass_levels(int swap, const void* x, void* X, int logn, int64_t batch, int seg_log2,
+                         int nthr, int fwd, int bwd, int chain) {
+  if (logn < 4 || logn > 24 || batch < 1 || nthr < 1) return -1;
+  if (fwd < 1 || fwd > 5 || bwd < 1 || bwd > 5 || chain < 1 || chain > 5) return -1;
+  std::vector<float> sec = secants(logn);
+  const qftk::MpLevels lv{fwd, bwd, chain};
+  return swap ? multipass_impl<0, true>(x, X, logn, batch, seg_log2, nthr, sec.data(), lv)
+              : multipass_impl<0, false>(x, X, logn, batch, seg_log2, nthr, sec.data(), lv);
+}
+
+// The library's schedule cache (host code shared with libqft.so).
+int emu_cache_store(const char* path, const char* key, const char* name) {
+  return qftk::schedule_cache_store(path, key, name) ? 1 : 0;
+}
+
+// 1 and the name in out[0 .. cap) if the key is found, else 0.
+int emu_cache_lookup(const char* path, const char* key, char* out, int cap) {
+  std::string name;
+  if (!qftk::schedule_cache_lookup(path, key, name) || cap < 1) return 0;
+  std::strncpy(out, name.c_str(), (size_t)cap - 1);
+  out[cap - 1] = '\0';
+  return 1;
+}
+
+// The cache path the library would use (environment read now).
+int emu_cache_path(char* out, int cap) {
+  const std::string p = qftk::schedule_cache_path();
+  if (cap < 1) return -1;
+  std::strncpy(out, p.c_str(), (size_t)cap - 1);
+  out[cap - 1] = '\0';
+  return (int)p.size();
 }
 
 }  // extern "C"

@@ -151,6 +151,24 @@ def test_two_pass_small(emu, mc_log2, swap):
     assert D.relative_l2(out, _ref(x, swap=bool(swap))).max() <= _tol(logn)
 
 
+@pytest.mark.parametrize("logn,seg", [(12, 3), (14, 5)])
+def test_multipass_level_splits_agree(emu, logn, seg):
+    """Every split of the global passes that a multi-pass plan offers as a
+    schedule (most forward rounds / backward rounds / chain levels per pass)
+    computes the same rounds and levels: bit-identical results."""
+    x = _as_c64(workloads.normal(700 + logn, (2, 1 << logn)))
+    outs = []
+    for f, b, c in [(4, 5, 5), (3, 5, 5), (4, 4, 5), (4, 5, 4), (3, 4, 4), (5, 5, 5), (1, 1, 1)]:
+        out = np.zeros_like(x)
+        races = emu.emu_multipass_levels(0, x.ctypes.data, out.ctypes.data, logn, 2, seg, 32,
+                                         f, b, c)
+        assert races == 0, (f, b, c, races)
+        outs.append(out)
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    assert D.relative_l2(outs[0], _ref(x)).max() <= _tol(logn)
+
+
 @pytest.mark.parametrize("mc_log2,batch", [(3, 19), (5, 11), (7, 9), (10, 17)])
 @pytest.mark.parametrize("grid", [32, 64])
 def test_two_pass_persistent(emu, mc_log2, batch, grid):

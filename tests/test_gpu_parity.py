@@ -8,6 +8,7 @@ FP16 storage adds the output rounding (2^-11 relative per element) to the bin
 bound and is held to 1e-3 in relative L2.
 """
 import ctypes
+import json
 import sys
 
 import numpy as np
@@ -539,3 +540,49 @@ def test_two_streams_share_no_scratch():
     torch.cuda.synchronize()
     check(outs["a"].cpu().numpy(), OB.cdft(xa.astype(np.complex128)), 16, what="stream a")
     check(outs["b"].cpu().numpy(), OB.cdft(xb.astype(np.complex128)), 16, what="stream b")
+
+
+@pytest.mark.parametrize("logn,B", [(18, 2), (12, 64)])
+def test_stage_schedules_agree_and_autotune_is_cached(logn, B, tmp_path, monkeypatch):
+    """A uniform plan's schedules (multi-pass: splits of the global passes;
+    tile sizes: the specialised kernel and the size-generic persistent kernel
+    with each tile size) give bit-identical results; autotune keeps the
+    fastest and records it in the schedule cache, and a new plan of the same
+    shape starts on the cached schedule (also one written by hand)."""
+    cache = tmp_path / "schedules.json"
+    monkeypatch.setenv("QFT_SCHEDULE_CACHE", str(cache))
+    say(f"stage schedules: N=2^{logn} B={B}")
+    x = torch.from_numpy(workloads.normal(5100 + logn, (B, 1 << logn))).to(DEV)
+    p = qft.Plan(logn, B)
+    names = p.schedules
+    say(f"schedules {names}")
+    assert len(names) > 1 and p.schedule == 0
+    outs = []
+    for i in range(len(names)):
+        p.schedule = i
+        outs.append(p.forward(x))
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs[1:], 1):
+        assert torch.equal(o, outs[0]), names[i]
+    check(outs[0].cpu().numpy(), ref_fwd(x.cpu().numpy()), logn, what=f"2^{logn} schedules")
+    times = p.autotune(x, reps=2)
+    best = names[p.schedule]
+    assert best == min(times, key=times.get)
+    doc = json.load(open(cache))
+    assert best in doc["entries"].values()
+    p2 = qft.Plan(logn, B)
+    assert p2.schedules[p2.schedule] == best
+    # a hand-written entry naming another schedule is followed
+    key = [k for k, v in doc["entries"].items() if v == best][0]
+    other = names[-1] if best != names[-1] else names[0]
+    doc["entries"][key] = other
+    json.dump(doc, open(cache, "w"))
+    p3 = qft.Plan(logn, B)
+    assert p3.schedules[p3.schedule] == other
+    assert torch.equal(p3.forward(x), outs[0])
+    # an entry naming no schedule of the plan is ignored
+    doc["entries"][key] = "no-such-schedule"
+    json.dump(doc, open(cache, "w"))
+    assert qft.Plan(logn, B).schedule == 0
+    for q in (p, p2, p3):
+        q.close()
