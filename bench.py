@@ -181,10 +181,16 @@ def extra_workloads(dev, stream):
     x3t = torch.from_numpy(x3).to(dev)
     y3 = torch.empty_like(x3t)
     p3 = qft.Plan(24, 1)
+    ms3_default = time_ms(lambda: qft.qft_exec_fwd(p3.handle, x3t.data_ptr(), y3.data_ptr(), sp),
+                          stream, 10, 2)
+    tuned3 = p3.autotune(x3t, y3, reps=5)  # splits of the global passes
     ms3 = time_ms(lambda: qft.qft_exec_fwd(p3.handle, x3t.data_ptr(), y3.data_ptr(), sp),
                   stream, 10, 2)
     out["c3_single_large"] = {
         "workload": "c3: N=2^24 x 1, 8 tones + N(0, 1e-3) noise, seed 2 (multi-pass path)",
+        "default_schedule_ms": round(ms3_default, 5),
+        "autotuned_schedule": p3.schedules[p3.schedule],
+        "schedule_ms": {k: round(v, 5) for k, v in tuned3.items()},
         "ms": round(ms3, 5), "GBps": round(p3.info["algo_bytes"] / (ms3 * 1e-3) / 1e9, 1),
         "GFLOPs_5nlogn": round(p3.info["flops_5nlogn"] / (ms3 * 1e-3) / 1e9, 1),
     }
@@ -274,7 +280,46 @@ def cpu_baseline(x, log2n, min_seconds=10.0):
     gflops = 5.0 * N * log2n * B * passes / dt / 1e9
     return X, dict(value=round(gflops, 3), unit="GFLOP/s", cores=threads, kind="oracle",
                    sample=f"{passes} passes over the full batch ({B} transforms of N=2^{log2n}), "
-                          f"FP64 recursive improved QFT in C, {dt:.1f} s wall")
+                          f"FP64 recursive improved QFT in C, {dt:.1f} s wall",
+                   legs=cpu_legs())
+
+
+def cpu_legs(min_seconds=3.0):
+    """The other CPU legs of the baseline: the FP64 O(N^2) DFT by its
+    definition (numpy) on the c1 workload, and one N = 2^24 transform of the
+    C oracle on a single thread."""
+    import workloads
+    from oracle import build as OB
+    from oracle import direct as D
+    legs = {}
+    x1 = workloads.make("c1").astype(np.complex128)
+    N1, B1 = x1.shape[1], x1.shape[0]
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        D.dft(x1)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds:
+            break
+    legs["direct_dft_c1"] = dict(
+        value=round(5.0 * N1 * 10 * B1 * reps / dt / 1e9, 3), unit="GFLOP/s (5N log2N)",
+        ms_per_batch=round(1e3 * dt / reps, 2), threads="numpy/BLAS default",
+        sample=f"{reps} O(N^2) passes over c1 ({B1} x N=2^10), {dt:.1f} s wall")
+    x3, _, _ = workloads.make("c3")
+    x3 = np.ascontiguousarray(x3.astype(np.complex128))
+    prev = OB.threads()
+    OB.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        OB.cdft(x3)
+        dt = time.perf_counter() - t0
+    finally:
+        OB.set_threads(prev)
+    N3 = x3.shape[1]
+    legs["c3_single_thread"] = dict(
+        value=round(5.0 * N3 * 24 / dt / 1e9, 3), unit="GFLOP/s (5N log2N)", ms=round(1e3 * dt, 1),
+        threads=1, sample="one N=2^24 transform (c3), FP64 recursive improved QFT in C")
+    return legs
 
 
 def main():
@@ -321,6 +366,7 @@ def main():
         else:
             qft.qft_exec_fwd(plan.handle, xt.data_ptr(), yt.data_ptr(), sp)
 
+    tuned = {} if args.calib_copy else plan.autotune(xt, yt, reps=5)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -364,6 +410,8 @@ def main():
                         "re/im N(0,1) seed 1",
             "log2n": log2n, "batch": B, "storage": "complex64",
         },
+        "schedule": plan.schedules[plan.schedule],
+        "schedule_ms": {k: round(v, 5) for k, v in tuned.items()},
         "roofline": {
             "bound": "hbm",
             "kernel": "qft_exec_fwd: both launches of the two-pass path (tp_a2_kernel gather + "
