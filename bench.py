@@ -196,6 +196,21 @@ def extra_workloads(dev, stream):
     }
     p3.close()
     del x3t, y3
+    # fixed point (QFT_I32): complex int32 pairs, one workgroup per transform
+    fx = {}
+    for lg, nb in ((12, 4096), (16, 64)):
+        rng = np.random.default_rng(6 + lg)
+        xi = torch.from_numpy(rng.integers(-(1 << (28 - lg)), 1 << (28 - lg), (nb, 1 << lg, 2))
+                              .astype(np.int32)).to(dev)
+        yi = torch.empty_like(xi)
+        fp = qft.FixedPlan(lg, nb)
+        fms = time_ms(lambda: qft.qft_exec_fwd(fp.handle, xi.data_ptr(), yi.data_ptr(), sp),
+                      stream, 10, 2)
+        fx[f"N=2^{lg} x {nb}"] = {"ms": round(fms, 5),
+                                  "GBps": round(fp.info["algo_bytes"] / (fms * 1e-3) / 1e9, 1)}
+        fp.close()
+        del xi, yi
+    out["fixed_point_int32"] = fx
     # real input (rdft): 8192 real signals of N = 2^12 (two per transform slot)
     xr = torch.from_numpy(workloads.normal(5, (8192, 4096)).real.astype(np.float32)).to(dev)
     rp = qft.RealPlan(12, 8192)

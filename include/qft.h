@@ -46,7 +46,8 @@ typedef struct qft_plan_s* qft_plan_t;
 
 typedef enum {
     QFT_SUCCESS = 0,
-    QFT_ERROR_INVALID_VALUE = 1, /* null pointer, batch/count <= 0, bad dtype */
+    QFT_ERROR_INVALID_VALUE = 1, /* null pointer, batch/count <= 0, bad dtype (QFT_I32 is
+                                    accepted by qft_plan_create only) */
     QFT_ERROR_INVALID_SIZE = 2,  /* log2n outside [1, QFT_MAX_LOG2N] */
     QFT_ERROR_ALIGNMENT = 3,     /* pointer not aligned to the element size */
     QFT_ERROR_OVERLAP = 4,       /* in/out partially overlap */
@@ -58,7 +59,8 @@ typedef enum {
 
 typedef enum {
     QFT_C32 = 0, /* complex FP32 storage, FP32 compute */
-    QFT_C16 = 1  /* complex FP16 storage, FP32 compute */
+    QFT_C16 = 1, /* complex FP16 storage, FP32 compute */
+    QFT_I32 = 2  /* fixed point: complex int32 storage and integer arithmetic */
 } qft_dtype;
 
 #define QFT_MAX_LOG2N 24
@@ -75,6 +77,28 @@ typedef enum {
  */
 qft_status qft_plan_create(qft_plan_t* plan, int log2n, int64_t batch, qft_dtype dtype,
                            int device);
+
+/*
+ * Fixed point (dtype QFT_I32; Sec. 1 and Sec. 7 recommend the method where a
+ * multiplication costs more than an addition).  Uniform plans only, 1 <=
+ * log2n <= 16 (else QFT_ERROR_INVALID_SIZE); elements are interleaved
+ * {int32 re, im} (8 bytes).  Every addition and subtraction wraps modulo
+ * 2^32; the only multiplications are the secant conversions (eq. qft_38A)
+ * and the N = 8 base cases, by block-scaled constants: slice L (periodization
+ * 8L, the constants 1/(2 cos(pi (2m+1)/(4L))), m < L) has one shift s_L = 30 -
+ * e_L, e_L the binary exponent of its largest constant, and mantissas
+ * H = floor(h 2^s_L + 1/2) (FP64, rounded once); a product is the 64-bit
+ * w H rounded half up at bit s_L, kept to 32 bits.  The output is the exact
+ * DFT of the integer input up to those roundings, and is bit-identical to
+ * the integer recursion in the paper's order for any input.  Without
+ * overflow, i.e. for |Re x|, |Im x| <= 2^(28 - log2n) (the largest growth of
+ * an intermediate measured over all inputs is below 1.4 N per real signal
+ * for N <= 2^11, growing about 17% per doubling), it approximates X within
+ * the rounding of about N log2 N - 3N products.  The plan allocates the
+ * integer table and, for log2n > 12, 2*batch*N int32 pairs of scratch; exec
+ * runs one workgroup per transform (in LDS up to 2^12 points).
+ * qft_exec_bwd gives the adjoint by the same swap identity as below.
+ */
 
 /*
  * Plan for `count` transforms of possibly different lengths 2^log2n[i]

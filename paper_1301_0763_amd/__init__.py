@@ -19,7 +19,7 @@ import collections
 import threading
 
 from . import _lib
-from ._lib import (QFT_C16, QFT_C32, QFT_MAX_LOG2N, QFTError, qft_exec_bwd,
+from ._lib import (QFT_C16, QFT_C32, QFT_I32, QFT_MAX_LOG2N, QFTError, qft_exec_bwd,
                    qft_exec_dct0_dst0, qft_exec_fwd, qft_exec_fwd_static, qft_exec_rdft,
                    qft_last_hip_error,
                    qft_plan_autotune, qft_plan_create, qft_plan_create_real,
@@ -34,7 +34,7 @@ __all__ = [
     "qft_last_hip_error", "qft_plan_schedules", "qft_plan_schedule_name",
     "qft_plan_set_schedule", "qft_plan_autotune", "qft_plan_create_real", "qft_exec_rdft",
     "qft_exec_dct0_dst0", "qft_exec_fwd_static", "RealPlan", "rdft", "dct0", "dst0",
-    "QFT_C32", "QFT_C16", "QFT_MAX_LOG2N",
+    "QFT_C32", "QFT_C16", "QFT_I32", "QFT_MAX_LOG2N", "FixedPlan", "fft_fixed",
 ]
 
 
@@ -140,6 +140,49 @@ class UnevenPlan(Plan):
         self.dtype, self.device = dtype, device
         self.handle = qft_plan_create_uneven(self.log2n_list, dtype, device)
         self.info = qft_plan_info(self.handle)
+
+
+class FixedPlan:
+    """Fixed-point plan (qft_plan_create with QFT_I32): `batch` transforms of
+    2^log2n points, complex int32 pairs as int32 tensors [..., N, 2]."""
+
+    def __init__(self, log2n, batch, device=0):
+        self.log2n, self.batch, self.device = int(log2n), int(batch), device
+        self.handle = qft_plan_create(log2n, batch, QFT_I32, device)
+        self.info = qft_plan_info(self.handle)
+
+    def _check(self, x, y):
+        torch = _torch()
+        for t in (x, y):
+            if not (t.is_cuda and t.is_contiguous() and t.dtype == torch.int32):
+                raise ValueError("tensors must be contiguous int32 GPU tensors")
+            if t.numel() != 2 * self.info["total_points"]:
+                raise ValueError("tensor size does not match the plan")
+
+    def forward(self, x, out=None):
+        torch = _torch()
+        out = torch.empty_like(x) if out is None else out
+        self._check(x, out)
+        qft_exec_fwd(self.handle, x.data_ptr(), out.data_ptr(), _stream_ptr(x.device))
+        return out
+
+    def adjoint(self, X, out=None):
+        torch = _torch()
+        out = torch.empty_like(X) if out is None else out
+        self._check(X, out)
+        qft_exec_bwd(self.handle, X.data_ptr(), out.data_ptr(), _stream_ptr(X.device))
+        return out
+
+    def close(self):
+        if self.handle:
+            qft_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _real_code(t):
@@ -269,6 +312,21 @@ def _plan_for(x):
             p = Plan(log2n, batch, key[2], dev)
             _cache[key] = p
     return p
+
+
+def fft_fixed(x):
+    """Fixed-point forward transform of int32 tensors [..., N, 2] (re, im)."""
+    x = x.contiguous()
+    N = x.shape[-2]
+    log2n = _log2n(N)
+    dev = _dev_index(x)
+    key = ("fixed", log2n, x.numel() // (2 * N), dev, _stream_ptr(x.device))
+    with _cache_lock:
+        p = _cache.get(key)
+        if p is None:
+            p = FixedPlan(log2n, key[2], dev)
+            _cache[key] = p
+    return p.forward(x)
 
 
 def fft(x):

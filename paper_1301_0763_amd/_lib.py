@@ -21,6 +21,7 @@ QFT_ERROR_SCRATCH = 8
 
 QFT_C32 = 0
 QFT_C16 = 1
+QFT_I32 = 2
 QFT_MAX_LOG2N = 24
 
 _lib = None

@@ -1,8 +1,9 @@
 """Builds the gfx950 library ``libqft.so`` in-tree.
 
-Twenty-three translation units compile in parallel (at most MAX_JOBS or one
+Twenty-four translation units compile in parallel (at most MAX_JOBS or one
 per CPU at a time) and link into one shared library: ``csrc/qft_lib.hip``
-(plans, C ABI, two-pass kernels), ``csrc/qft_multipass.hip`` once per
+(plans, C ABI, two-pass kernels), ``csrc/qft_fixed.hip`` (the fixed-point
+kernels), ``csrc/qft_multipass.hip`` once per
 storage type (``-DQFT_MP_DT=0`` complex FP32, ``=1`` complex FP16) and
 ``csrc/qft_tiles.hip`` once per storage type (``-DQFT_TILE_DT``), tile size
 (``-DQFT_TILE_TL=10 .. 14``) and direction (``-DQFT_TILE_SWAP=0`` forward,
@@ -22,9 +23,10 @@ CSRC = os.path.join(HERE, "csrc")
 SRC = os.path.join(CSRC, "qft_lib.hip")
 TILES = os.path.join(CSRC, "qft_tiles.hip")
 MULTI = os.path.join(CSRC, "qft_multipass.hip")
-DEPS = [SRC, TILES, MULTI] + [os.path.join(CSRC, f) for f in
+FIXED = os.path.join(CSRC, "qft_fixed.hip")
+DEPS = [SRC, TILES, MULTI, FIXED] + [os.path.join(CSRC, f) for f in
                        ("qft_device.hpp", "qft_schedule.hpp", "qft_kernels.hpp",
-                        "qft_cache.hpp")]
+                        "qft_cache.hpp", "qft_fixed.hpp")]
 LIB = os.path.join(HERE, "libqft.so")
 ROOT = os.path.dirname(HERE)
 HEADER = os.path.join(ROOT, "include", "qft.h")
@@ -54,7 +56,7 @@ def build(verbose=False):
         units = [(TILES, ["-DQFT_TILE_DT=%d" % dt, "-DQFT_TILE_TL=%d" % tl,
                           "-DQFT_TILE_SWAP=%d" % sw], "tiles_%d_%d_%d.o" % (dt, tl, sw))
                  for tl in (14, 13, 12, 11, 10) for dt in (0, 1) for sw in (0, 1)]
-        units[0:0] = [(SRC, [], "lib.o")] + [
+        units[0:0] = [(SRC, [], "lib.o"), (FIXED, [], "fixed.o")] + [
             (MULTI, ["-DQFT_MP_DT=%d" % dt], "multipass_%d.o" % dt) for dt in (0, 1)]
         # at most one compiler per CPU (each takes ~1-2 GB)
         jobs = max(1, min(len(units), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))

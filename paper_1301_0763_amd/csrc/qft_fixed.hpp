@@ -1,0 +1,295 @@
+// Fixed-point (integer) improved-QFT transform: the fixed-point use the
+// paper recommends the method for (Sec. 1, Sec. 7), on gfx950.
+//
+// Number format: complex samples as int2 (real, imaginary), every addition
+// and subtraction wrapping modulo 2^32; the only multiplications are the
+// secant conversions of eq. qft_38A (and the two N = 8 base cases, which use
+// the slice L = 1), with block-scaled constants: slice L (periodization 8L)
+// holds mantissas H_L(m) = round(2^s_L / (2 cos(pi (2m+1) / (4L)))) < 2^30
+// with one shift s_L per slice, and a product w * h is the 64-bit w H
+// rounded half up at bit s_L, kept to 32 bits.  Every output is therefore a
+// fixed function of the input integers: any order of the additions gives the
+// same result, and the heap layout below computes exactly the values of the
+// paper's recursion.
+//
+// Work layout: the heap layout of qft_device.hpp (sides of N/2 cells, the
+// DCT-II / DST-II block of periodization P at cells [P/4, P/2) of its side,
+// c(0) in cell 0, c(N/2) in cell N/2), one workgroup per transform, one
+// round or chain level per pass:
+//   fold             x -> c, d in heap order
+//   forward rounds   S = N/4 .. 2, in place on closed quads of cells
+//   backward rounds  S = 2 .. N/4, from one buffer into the other
+//   chain levels     P = 2 .. N, in place on closed groups
+//   combine          X(k), X(N-k) from the DCT cell k and the DST cell k
+// The buffers live in LDS (N <= 2^12) or in global scratch (2N cells per
+// transform).  This path is written for exactness and simplicity, not speed:
+// it takes one workgroup barrier per round and level.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+#ifndef QFT_HD
+#define QFT_HD __host__ __device__ __forceinline__
+#endif
+
+namespace qftk {
+namespace fx {
+
+QFT_HD int iadd(int a, int b) { return (int)((uint32_t)a + (uint32_t)b); }
+QFT_HD int isub(int a, int b) { return (int)((uint32_t)a - (uint32_t)b); }
+QFT_HD int2 add(int2 a, int2 b) { return make_int2(iadd(a.x, b.x), iadd(a.y, b.y)); }
+QFT_HD int2 sub(int2 a, int2 b) { return make_int2(isub(a.x, b.x), isub(a.y, b.y)); }
+
+// w * h with h = H / 2^s: the 64-bit product rounded half up at bit s, kept
+// to the low 32 bits (two's complement).
+QFT_HD int qmul(int w, int H, int s) {
+  const int64_t p = (int64_t)w * (int64_t)H + ((int64_t)1 << (s - 1));
+  return (int)(uint32_t)(uint64_t)(p >> s);
+}
+QFT_HD int2 mul(int2 w, int H, int s) { return make_int2(qmul(w.x, H, s), qmul(w.y, H, s)); }
+
+// Constant table of the transform: H[L + m] (L = 1, 2, .., N/8, m < L) and
+// the shift of slice L = 2^lg in shift[lg].
+struct Table {
+  const int* H;
+  const int* shift;
+};
+
+QFT_HD int ilog2(int v) {
+  int r = 0;
+  while ((1 << (r + 1)) <= v) ++r;
+  return r;
+}
+
+// Heap cell p >= 1 of a side holds the sample n = (2m + 1) N / (4M), M the
+// largest power of two <= p, m = p - M.
+QFT_HD int cell_sample(int p, int logn) {
+  const int lgM = ilog2(p);
+  return (2 * (p - (1 << lgM)) + 1) << (logn - 2 - lgM);
+}
+
+// Fold of x (Sec. 4.2: c(n) = x(n) + x(N-n), d(n) = x(n) - x(N-n)) into the
+// heap: DCT side cells [0, N/2), DST side cells [N/2, N) (cell N/2 = c(N/2)).
+template <typename XP, typename WP>
+QFT_HD void fold(XP x, WP W, int logn, int tid, int nthr) {
+  const int N = 1 << logn, h = N >> 1;
+  for (int p = tid; p < h; p += nthr) {
+    if (p == 0) {
+      W[0] = x[0];
+      W[h] = x[h];
+    } else {
+      const int n = cell_sample(p, logn);
+      const int2 a = x[n], b = x[N - n];
+      W[p] = add(a, b);
+      W[h + p] = sub(a, b);
+    }
+  }
+}
+
+// Forward round S (Sec. 5.2.2-5.2.3, eqs. qft_1/qft_2, qft_38A) on every
+// segment [jS, (j+1)S), j >= 1, of both sides: u(p) = y(p) + y(S-1-p),
+// v(p) = y(p) - y(S-1-p) for p < S/2; DCT side u -> p, v h_{S/2}(p) -> S/2+p;
+// DST side v -> p, u h_{S/2}(p) -> S/2+p.  Item = one closed quad of cells
+// {p, S/2-1-p, S/2+p, S-1-p} (p < S/4; the pair {0, 1} when S = 2).
+template <typename WP>
+QFT_HD void fwd_round(WP W, int logn, int S, Table tab, int tid, int nthr) {
+  const int h = 1 << (logn - 1);
+  const int L = S >> 1;
+  const int s = tab.shift[ilog2(L)];
+  const int* H = tab.H + L;
+  const int segs = h / S - 1;               // j = 1 .. h/S - 1
+  const int quads = S >= 4 ? S >> 2 : 1;
+  const int items = 2 * segs * quads;
+  for (int i = tid; i < items; i += nthr) {
+    const int side = i / (segs * quads);
+    const int r = i - side * segs * quads;
+    const int j = 1 + r / quads, p = r - (r / quads) * quads;
+    auto y = W + side * h + j * S;
+    const bool dst = side != 0;
+    if (S == 2) {
+      const int2 a = y[0], b = y[1];
+      const int2 u = add(a, b), v = sub(a, b);
+      y[0] = dst ? v : u;
+      y[1] = mul(dst ? u : v, H[0], s);
+    } else {
+      const int pa = p, pb = L - 1 - p, pc = L + p, pd = S - 1 - p;
+      const int2 a = y[pa], b = y[pb], c = y[pc], d = y[pd];
+      const int2 u1 = add(a, d), v1 = sub(a, d);  // pair (p, S-1-p)
+      const int2 u2 = add(b, c), v2 = sub(b, c);  // pair (L-1-p, L+p)
+      y[pa] = dst ? v1 : u1;
+      y[pc] = mul(dst ? u1 : v1, H[pa], s);
+      y[pb] = dst ? v2 : u2;
+      y[pd] = mul(dst ? u2 : v2, H[pb], s);
+    }
+  }
+}
+
+// Backward round S (eq. qft_4B interleave, eqs. qft_38B corrected / qft_38C,
+// the dst_oo special case) from Win into Wout: for every segment j >= 1 with
+// halves A = [jS, jS + S/2) and T = [jS + S/2, (j+1)S):
+//   DCT: Y(2i) = A(i), Y(2i+1) = T(i) + T(i+1), T(S/2) = 0;
+//   DST: Y(2i+1) = A(i), Y(2i) = T(i-1) + T(i), T(-1) = 0;
+// the head cells [0, S) of each side are carried over unchanged.
+template <typename RP, typename WP>
+QFT_HD void bwd_round(RP Win, WP Wout, int logn, int S, int tid, int nthr) {
+  const int h = 1 << (logn - 1);
+  const int L = S >> 1;
+  for (int c = tid; c < 2 * h; c += nthr) {
+    const int side = c >= h ? 1 : 0;
+    const int q = c - side * h;
+    if (q < S) {
+      Wout[c] = Win[c];
+      continue;
+    }
+    const int j = q / S, m = q - j * S, i = m >> 1;
+    auto a = Win + side * h + j * S;
+    auto t = a + L;
+    int2 v;
+    if (side == 0) {
+      if ((m & 1) == 0) v = a[i];
+      else v = (i + 1 < L) ? add(t[i], t[i + 1]) : (int2)t[i];
+    } else {
+      if ((m & 1) != 0) v = a[i];
+      else v = (i >= 1) ? add(t[i - 1], t[i]) : (int2)t[i];
+    }
+    Wout[c] = v;
+  }
+}
+
+// Chain level P (eqs. qft_5C, qft_5D, qft_6), both sides, in place.
+//   DCT (P >= 4): E = D_{P/2} in cells [0, P/4) and E(P/4) in the top cell
+//     N/2, O(k) in cell P/4 + k; D(k) = E(k) + O(k), D(P/2-k) = E(k) - O(k)
+//     (k < P/4), D(P/4) = E(P/4); D(k) -> cell k, D(P/2) -> top cell.
+//     P = 2: D(0) = c(0) + c(N/2) -> cell 0, D(1) = c(0) - c(N/2) -> top.
+//     Groups: k = 0 (cells 0, P/4, top), k with P/4 - k (1 <= k < P/8), P/8.
+//   DST (P >= 8): E(k) in cell k (1 <= k < P/4), O(k) in cell P/4 + k - 1
+//     (1 <= k <= P/4); S(k) = O(k) + E(k), S(P/2-k) = O(k) - E(k), S(P/4) =
+//     O(P/4); S(k) -> cell k.  Groups: k = 1 with O(P/4), k with P/4 + 1 - k
+//     (2 <= k <= P/8).
+template <typename WP>
+QFT_HD void chain_level(WP W, int logn, int P, int tid, int nthr) {
+  const int h = 1 << (logn - 1);
+  auto dc = W;
+  auto ds = W + h;
+  auto top = W + h;  // DST cell 0 holds the DCT's top value
+  const int q = P >> 2;
+  const int dct_items = P == 2 ? 1 : 1 + (P >= 8 ? P / 8 : 0);
+  const int dst_items = P >= 8 ? P / 8 : 0;
+  for (int i = tid; i < dct_items + dst_items; i += nthr) {
+    if (i < dct_items) {
+      if (P == 2) {
+        const int2 e = dc[0], t = top[0];
+        dc[0] = add(e, t);
+        top[0] = sub(e, t);
+      } else if (i == 0) {
+        const int2 e0 = dc[0], o0 = dc[q], eq = top[0];
+        dc[0] = add(e0, o0);
+        top[0] = sub(e0, o0);
+        dc[q] = eq;
+      } else {
+        const int k = i, kp = q - k;  // k = P/8 pairs with itself
+        const int2 ek = dc[k], ok = dc[q + k];
+        if (kp != k) {
+          const int2 ep = dc[kp], op = dc[q + kp];
+          dc[kp] = add(ep, op);
+          dc[(P >> 1) - kp] = sub(ep, op);
+        }
+        dc[k] = add(ek, ok);
+        dc[(P >> 1) - k] = sub(ek, ok);
+      }
+    } else {
+      const int k = 1 + (i - dct_items);  // 1 .. P/8
+      if (k == 1) {
+        const int2 e1 = ds[1], o1 = ds[q], oq = ds[(P >> 1) - 1];
+        ds[1] = add(o1, e1);
+        ds[(P >> 1) - 1] = sub(o1, e1);
+        ds[q] = oq;
+      } else {
+        const int kp = q + 1 - k;
+        const int2 ek = ds[k], ok = ds[q + k - 1];
+        const int2 ep = ds[kp], op = ds[q + kp - 1];
+        ds[k] = add(ok, ek);
+        ds[(P >> 1) - k] = sub(ok, ek);
+        ds[kp] = add(op, ep);
+        ds[(P >> 1) - kp] = sub(op, ep);
+      }
+    }
+  }
+}
+
+// Combine (Sec. 4.1): with C = DCT cell k = (Cr, Ci) and S = DST cell k =
+// (Sr, Si), X(k) = (Cr + Si, Ci - Sr), X(N-k) = (Cr - Si, Ci + Sr) for
+// 0 < k < N/2; X(0) = C(0), X(N/2) = the top cell.
+template <typename WP, typename XP>
+QFT_HD void combine(WP W, XP X, int logn, int tid, int nthr) {
+  const int N = 1 << logn, h = N >> 1;
+  for (int k = tid; k <= h; k += nthr) {
+    if (k == 0) {
+      X[0] = W[0];
+    } else if (k == h) {
+      X[h] = W[h];
+    } else {
+      const int2 c = W[k], s = W[h + k];
+      X[k] = make_int2(iadd(c.x, s.y), isub(c.y, s.x));
+      X[N - k] = make_int2(isub(c.x, s.y), iadd(c.y, s.x));
+    }
+  }
+}
+
+// Host: the integer constant table for transforms up to 2^log2n_max points
+// (N/4 mantissas, layout of the FP32 table: entry L + m), shift[lg] for the
+// slice L = 2^lg.  h_L(m) = 1/(2 cos(pi (2m+1) / (4L))) in FP64 (C library
+// cosine), e_L the binary exponent of h_L(L-1) (h < 2^e_L), s_L = 30 - e_L,
+// H_L(m) = floor(h_L(m) 2^s_L + 1/2).  Entry 0 is unused (0).
+inline void fill_table_q(int* H, int* shift, int log2n_max) {
+  const int64_t nt = ((int64_t)1 << (log2n_max < 3 ? 3 : log2n_max)) / 4;
+  H[0] = 0;
+  int lg = 0;
+  for (int64_t L = 1; 2 * L <= nt; L *= 2, ++lg) {
+    double hmax = 0.0;
+    for (int64_t m = 0; m < L; ++m) {
+      const double hv = 1.0 / (2.0 * std::cos(M_PI * (double)(2 * m + 1) / (double)(4 * L)));
+      if (m == L - 1) hmax = hv;
+    }
+    int e = 0;
+    (void)std::frexp(hmax, &e);
+    const int sh = 30 - e;
+    shift[lg] = sh;
+    for (int64_t m = 0; m < L; ++m) {
+      const double hv = 1.0 / (2.0 * std::cos(M_PI * (double)(2 * m + 1) / (double)(4 * L)));
+      H[L + m] = (int)std::floor(hv * std::ldexp(1.0, sh) + 0.5);
+    }
+  }
+}
+
+// One transform of 2^logn points, x -> X, with heap buffers B0, B1 of N
+// cells each; every pass ends with sync() (a workgroup barrier).
+template <typename XP, typename OP, typename BP, class Sync>
+QFT_HD void transform(XP x, OP X, BP B0, BP B1, int logn, Table tab, int tid, int nthr,
+                      Sync sync) {
+  fold(x, B0, logn, tid, nthr);
+  sync();
+  for (int S = (1 << logn) >> 2; S >= 2; S >>= 1) {
+    fwd_round(B0, logn, S, tab, tid, nthr);
+    sync();
+  }
+  BP cur = B0, oth = B1;
+  for (int S = 2; S <= ((1 << logn) >> 2); S <<= 1) {
+    bwd_round(cur, oth, logn, S, tid, nthr);
+    sync();
+    BP t = cur;
+    cur = oth;
+    oth = t;
+  }
+  for (int P = 2; P <= (1 << logn); P <<= 1) {
+    chain_level(cur, logn, P, tid, nthr);
+    sync();
+  }
+  combine(cur, X, logn, tid, nthr);
+}
+
+}  // namespace fx
+}  // namespace qftk

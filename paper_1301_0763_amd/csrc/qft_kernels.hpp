@@ -109,4 +109,12 @@ template <int DT>
 hipError_t launch_multipass_real(int kind, const RealArgs& a, int log2n, int64_t rows,
                                  const float* sec, float2* W0, float2* W1, hipStream_t st);
 
+// Fixed-point (QFT_I32) transforms of 2^log2n points (1 <= log2n <=
+// kFixedMaxLog2), `batch` of them, complex int32 pairs in and out; H and
+// shift are the device copies of fx::fill_table_q's table; scratch holds
+// 2 * batch * 2^log2n int2 cells when log2n > 12 (else unused).
+constexpr int kFixedMaxLog2 = 16;
+hipError_t launch_fixed(bool swap, const void* in, void* out, int log2n, int64_t batch,
+                        const int* H, const int* shift, int2* scratch, hipStream_t st);
+
 }  // namespace qftk

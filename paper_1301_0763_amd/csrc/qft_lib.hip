@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "qft_cache.hpp"
+#include "qft_fixed.hpp"
 #include "qft_kernels.hpp"
 #include "qft_schedule.hpp"
 #include "../../include/qft.h"
@@ -140,6 +141,9 @@ struct qft_plan_s {
   int chosen = 0;
   std::vector<LargeItem> large;  // common to every schedule
   std::vector<void*> dev_allocs;  // tile lists of the groups (shared between schedules)
+  bool fixed = false;              // QFT_I32 plan: the fixed-point transform
+  int* d_fxH = nullptr;            // its integer constant table (N/4 mantissas)
+  int* d_fxShift = nullptr;        // and the shift of each slice
   std::string cache_key;          // schedule-cache key (device and plan shape)
   bool from_cache = false;        // the chosen schedule came from the cache
 };
@@ -190,7 +194,7 @@ qft_status check_device(int device, int* cus) {
 std::string plan_key(const qft_plan_s* p, const char* kind, const int32_t* sizes,
                      int64_t count) {
   std::string k = "gfx950/" + std::to_string(p->cus) + "cu/" + kind + "/" +
-                  (p->dtype == QFT_C32 ? "c32" : "c16") + "/";
+                  (p->dtype == QFT_C32 ? "c32" : p->dtype == QFT_C16 ? "c16" : "i32") + "/";
   if (sizes) {
     uint64_t h = 1469598103934665603ull;
     for (int64_t i = 0; i < count; ++i) {
@@ -228,6 +232,8 @@ void free_plan(qft_plan_s* p) {
   if (!p) return;
   if (p->d_sec) (void)hipFree(p->d_sec);
   if (p->d_work) (void)hipFree(p->d_work);
+  if (p->d_fxH) (void)hipFree(p->d_fxH);
+  if (p->d_fxShift) (void)hipFree(p->d_fxShift);
   for (void* a : p->dev_allocs) (void)hipFree(a);
   delete p;
 }
@@ -367,9 +373,12 @@ qft_status run_schedule(const qft_plan_s* p, const Schedule& s, const void* in, 
   return QFT_SUCCESS;
 }
 
+// Bytes of one complex element of the plan's storage type.
+int64_t elem_size(qft_dtype dt) { return dt == QFT_C16 ? 4 : 8; }
+
 qft_status check_buffers(const qft_plan_s* plan, const void* in, const void* out) {
   if (!plan || !in || !out) return QFT_ERROR_INVALID_VALUE;
-  const int64_t esz = plan->dtype == QFT_C32 ? 8 : 4;
+  const int64_t esz = elem_size(plan->dtype);
   if (((uintptr_t)in % esz) != 0 || ((uintptr_t)out % esz) != 0) return QFT_ERROR_ALIGNMENT;
   const int64_t bytes = plan->total_points * esz;
   const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
@@ -380,6 +389,12 @@ qft_status check_buffers(const qft_plan_s* plan, const void* in, const void* out
 template <bool SWAP>
 qft_status exec_sched(const qft_plan_s* plan, int sched, const void* in, void* out,
                       hipStream_t st) {
+  if (plan->fixed) {
+    const hipError_t e = qftk::launch_fixed(SWAP, in, out, plan->log2n, plan->batch,
+                                            plan->d_fxH, plan->d_fxShift, (int2*)plan->d_work,
+                                            st);
+    return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
+  }
   const Schedule& s = plan->schedules[sched];
   return plan->dtype == QFT_C32 ? run_schedule<0, SWAP>(plan, s, in, out, st)
                                 : run_schedule<1, SWAP>(plan, s, in, out, st);
@@ -393,6 +408,30 @@ qft_status exec_impl(qft_plan_t plan, const void* in, void* out, void* stream) {
   DeviceGuard guard(plan->device);
   if (!guard.ok) return hip_fail(hipErrorInvalidDevice);
   return exec_sched<SWAP>(plan, plan->chosen, in, out, (hipStream_t)stream);
+}
+
+// The fixed-point plan (QFT_I32): integer constant table and, for N > 2^12,
+// two heap buffers of N int2 cells per transform.
+qft_status create_fixed(qft_plan_s* p) {
+  const int lg = std::max(p->log2n, 3);
+  const int64_t nt = ((int64_t)1 << lg) / 4;
+  std::vector<int> H((size_t)nt), shift(32, 0);
+  qftk::fx::fill_table_q(H.data(), shift.data(), lg);
+  QFT_HIP(hipMalloc(&p->d_fxH, nt * sizeof(int)));
+  QFT_HIP(hipMemcpy(p->d_fxH, H.data(), nt * sizeof(int), hipMemcpyHostToDevice));
+  QFT_HIP(hipMalloc(&p->d_fxShift, shift.size() * sizeof(int)));
+  QFT_HIP(hipMemcpy(p->d_fxShift, shift.data(), shift.size() * sizeof(int),
+                    hipMemcpyHostToDevice));
+  if (p->log2n > 12) {
+    const int64_t bytes = 2 * (p->batch << p->log2n) * (int64_t)sizeof(int2);
+    hipError_t e = hipMalloc(&p->d_work, bytes);
+    if (e != hipSuccess) {
+      g_last_hip_error = (int)e;
+      return QFT_ERROR_ALLOC;
+    }
+  }
+  p->schedules.push_back(Schedule{"fixed", {}, true, {}});
+  return QFT_SUCCESS;
 }
 
 // Byte range [p, p + n) of a real-input exec argument; null pointers are empty.
@@ -568,9 +607,12 @@ qft_status qft_plan_create(qft_plan_t* plan, int log2n, int64_t batch, qft_dtype
                            int device) {
   if (!plan) return QFT_ERROR_INVALID_VALUE;
   *plan = nullptr;
-  if (batch <= 0 || (dtype != QFT_C32 && dtype != QFT_C16)) return QFT_ERROR_INVALID_VALUE;
+  if (batch <= 0 || (dtype != QFT_C32 && dtype != QFT_C16 && dtype != QFT_I32))
+    return QFT_ERROR_INVALID_VALUE;
   if (log2n < 1 || log2n > QFT_MAX_LOG2N) return QFT_ERROR_INVALID_SIZE;
+  if (dtype == QFT_I32 && log2n > qftk::kFixedMaxLog2) return QFT_ERROR_INVALID_SIZE;
   if (batch > ((int64_t)1 << 40) >> log2n) return QFT_ERROR_INVALID_VALUE;
+  if (dtype == QFT_I32 && batch > 0x7fffffff) return QFT_ERROR_INVALID_VALUE;
   int cus = 0;
   qft_status s = check_device(device, &cus);
   if (s != QFT_SUCCESS) return s;
@@ -582,6 +624,16 @@ qft_status qft_plan_create(qft_plan_t* plan, int log2n, int64_t batch, qft_dtype
   p->batch = batch;
   p->max_log2n = log2n;
   add_costs(p, log2n, batch);
+  if (dtype == QFT_I32) {
+    p->fixed = true;
+    s = create_fixed(p);
+    if (s != QFT_SUCCESS) {
+      free_plan(p);
+      return s;
+    }
+    *plan = p;
+    return QFT_SUCCESS;
+  }
   if (log2n <= qftk::kMaxTileLog2) {
     // schedule 0: the kernel specialised for this size, one workgroup per
     // tile of 2^max(10, log2n) cells
@@ -784,7 +836,7 @@ qft_status qft_plan_destroy(qft_plan_t plan) {
 qft_status qft_plan_info(qft_plan_t plan, int64_t* total_points, int64_t* algo_bytes,
                          double* flops_5nlogn, double* flops_actual) {
   if (!plan) return QFT_ERROR_INVALID_VALUE;
-  const int64_t esz = plan->dtype == QFT_C32 ? 8 : 4;
+  const int64_t esz = elem_size(plan->dtype);
   if (total_points) *total_points = plan->total_points;
   if (algo_bytes) *algo_bytes = plan->real ? plan->real_algo_bytes : 2 * plan->total_points * esz;
   if (flops_5nlogn) *flops_5nlogn = plan->flops_5nlogn;

@@ -12,7 +12,8 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 SRC = os.path.join(HERE, "qft_emu.cpp")
 LIB = os.path.join(HERE, "libqft_emu.so")
 DEPS = [SRC] + [os.path.join(ROOT, "paper_1301_0763_amd", "csrc", f)
-                for f in ("qft_device.hpp", "qft_schedule.hpp", "qft_cache.hpp")]
+                for f in ("qft_device.hpp", "qft_schedule.hpp", "qft_cache.hpp",
+                          "qft_fixed.hpp")]
 
 
 def build(force=True):
@@ -43,9 +44,12 @@ def load():
     L.emu_cache_store.argtypes = [cp, cp, cp]
     L.emu_cache_lookup.argtypes = [cp, cp, ctypes.c_char_p, i]
     L.emu_cache_path.argtypes = [ctypes.c_char_p, i]
+    L.emu_fixed.argtypes = [vp, vp, i, i64, i]
+    L.emu_fixed_table.argtypes = [i, vp, vp]
     for f in (L.emu_multipass, L.emu_uneven, L.emu_twopass, L.emu_tile_s,
               L.emu_tile_real, L.emu_multipass_real, L.emu_race_model_check,
-              L.emu_multipass_levels, L.emu_cache_store, L.emu_cache_lookup, L.emu_cache_path):
+              L.emu_multipass_levels, L.emu_cache_store, L.emu_cache_lookup, L.emu_cache_path,
+              L.emu_fixed, L.emu_fixed_table):
         f.restype = i
     return L
 

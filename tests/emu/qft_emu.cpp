@@ -25,6 +25,7 @@
 
 #include "../../paper_1301_0763_amd/csrc/qft_cache.hpp"
 #include "../../paper_1301_0763_amd/csrc/qft_device.hpp"
+#include "../../paper_1301_0763_amd/csrc/qft_fixed.hpp"
 #include "../../paper_1301_0763_amd/csrc/qft_schedule.hpp"
 
 namespace {
@@ -134,6 +135,40 @@ struct TPtr {
   }
   Ref operator*() const { return (*this)[0]; }
   TPtr operator+(int64_t d) const { return TPtr{base, off + d, tr, size, ps}; }
+};
+
+// Tracked int2 cells (the fixed-point path).
+struct IRef {
+  int2* p;
+  int64_t cell;
+  Tracker* tr;
+  operator int2() const {
+    tr->logs[tl_slot].push_back({cell, tl_wave, tl_wp, tl_actor, false});
+    return *p;
+  }
+  IRef& operator=(int2 v) {
+    tr->logs[tl_slot].push_back({cell, tl_wave, tl_wp, tl_actor, true});
+    *p = v;
+    return *this;
+  }
+  IRef& operator=(const IRef& r) { return *this = (int2)r; }
+};
+
+struct IPtr {
+  int2* base;
+  int64_t off;
+  Tracker* tr;
+  int64_t size;
+  IRef operator[](int64_t i) const {
+    static int2 sink;
+    const int64_t c = off + i;
+    if (c < 0 || c >= size) {
+      tr->oob++;
+      return IRef{&sink, -1, tr};
+    }
+    return IRef{base + c, (int64_t)(uintptr_t)(base + c), tr};
+  }
+  IPtr operator+(int64_t d) const { return IPtr{base, off + d, tr, size}; }
 };
 
 // Row accesses of the kernels (pad_row in qft_device.hpp) on an emulated
@@ -700,6 +735,39 @@ int emu_race_model_check(int order, int same_wave) {
     (void)v;
   });
   return (int)tr.races;
+}
+
+// The fixed-point transform (qft_fixed.hpp) of `batch` complex int32
+// signals of 2^logn points, x, X as int32 pairs, one emulated workgroup of
+// nthr threads per transform with tracked heap buffers, input and output.
+// Returns the races found, or a negative code.
+int emu_fixed(const int32_t* x, int32_t* X, int logn, int64_t batch, int nthr) {
+  if (logn < 1 || logn > 16 || batch < 1 || nthr < 1) return -1;
+  const int64_t N = (int64_t)1 << logn;
+  std::vector<int> H((size_t)std::max<int64_t>(N / 4, 2)), shift(32);
+  qftk::fx::fill_table_q(H.data(), shift.data(), logn);
+  const qftk::fx::Table tab{H.data(), shift.data()};
+  int64_t races = 0;
+  for (int64_t b = 0; b < batch; ++b) {
+    std::vector<int2> b0((size_t)N), b1((size_t)N);
+    Tracker tr(nthr);
+    IPtr B0{b0.data(), 0, &tr, N}, B1{b1.data(), 0, &tr, N};
+    IPtr xi{(int2*)(const_cast<int32_t*>(x)) + b * N, 0, &tr, N};
+    IPtr Xo{(int2*)X + b * N, 0, &tr, N};
+    run_workgroup(nthr, tr, [&](int tid, auto sync, auto) {
+      qftk::fx::transform(xi, Xo, B0, B1, logn, tab, tid, nthr, sync);
+    });
+    if (tr.oob) return -100;
+    races += tr.races;
+  }
+  return (int)races;
+}
+
+// The library's integer constant table (host code of qft_fixed.hpp).
+int emu_fixed_table(int log2n, int32_t* H, int32_t* shift) {
+  if (log2n < 1 || log2n > 24) return -1;
+  qftk::fx::fill_table_q(H, shift, log2n);
+  return 0;
 }
 
 // Multi-pass path with a given split of the global passes (most forward

@@ -104,6 +104,21 @@ def test_static_exec_rejects_before_any_hip_call():
     assert f(16, 4, 0, p, p + 64, None) == _lib.QFT_ERROR_OVERLAP
 
 
+def test_fixed_point_plan_rejects():
+    """QFT_I32 (fixed point) is a uniform-plan dtype for log2n <= 16."""
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.qft_plan_create(ctypes.byref(h), 17, 1, _lib.QFT_I32, 0) == \
+        _lib.QFT_ERROR_INVALID_SIZE
+    arr = (ctypes.c_int32 * 2)(4, 5)
+    assert L.qft_plan_create_uneven(ctypes.byref(h), arr, 2, _lib.QFT_I32, 0) == \
+        _lib.QFT_ERROR_INVALID_VALUE
+    assert L.qft_plan_create_real(ctypes.byref(h), 8, 2, _lib.QFT_I32, 0) == \
+        _lib.QFT_ERROR_INVALID_VALUE
+    assert L.qft_exec_fwd_static(8, 2, _lib.QFT_I32, 1 << 20, 1 << 40, None) == \
+        _lib.QFT_ERROR_INVALID_VALUE
+
+
 def test_exec_and_info_reject_null_plan():
     L = _lib.lib()
     assert L.qft_exec_fwd(None, 8, 8, None) == _lib.QFT_ERROR_INVALID_VALUE

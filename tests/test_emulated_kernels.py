@@ -347,3 +347,36 @@ def _rdft_emu_ref(x):
     ref = re.astype(np.complex128)
     ref[..., 1:N // 2] += 1j * im
     return ref
+
+
+@pytest.mark.parametrize("logn", list(range(1, 12)) + [13])
+def test_fixed_point_emulated(emu, logn):
+    """The fixed-point kernel body (qft_fixed.hpp) run on the CPU with the
+    library's thread counts: bit-identical to the integer oracle, including
+    inputs that overflow (two's complement wrap), and race free."""
+    from oracle import qft_fixed as F
+    N = 1 << logn
+    rng = np.random.default_rng(900 + logn)
+    for lim in (1 << (28 - logn), 1 << 31):
+        x = rng.integers(-lim, lim, (2, N, 2)).astype(np.int32)
+        X = np.zeros_like(x)
+        races = emu.emu_fixed(x.ctypes.data, X.ctypes.data, logn, 2, 64 if logn <= 9 else 256)
+        assert races == 0
+        assert np.array_equal(X.astype(np.int64), F.cdft_fixed(x))
+
+
+def test_fixed_point_table_matches_oracle(emu):
+    """The library's integer constant table (host code) and the oracle's,
+    computed independently from the same definition, are identical."""
+    from oracle import qft_fixed as F
+    for r in (3, 8, 12, 16):
+        nt = (1 << r) // 4
+        H = np.zeros(nt, np.int32)
+        sh = np.zeros(32, np.int32)
+        assert emu.emu_fixed_table(r, H.ctypes.data, sh.ctypes.data) == 0
+        Ho, so = F.secant_table_q(r)
+        assert np.array_equal(H.astype(np.int64), Ho)
+        L, lg = 1, 0
+        while 2 * L <= nt:
+            assert sh[lg] == so[L]
+            L, lg = 2 * L, lg + 1

@@ -586,3 +586,33 @@ def test_stage_schedules_agree_and_autotune_is_cached(logn, B, tmp_path, monkeyp
     assert qft.Plan(logn, B).schedule == 0
     for q in (p, p2, p3):
         q.close()
+
+
+def _fixed_ref(x):
+    from oracle import qft_fixed as F
+    return F.cdft_fixed(x)
+
+
+@pytest.mark.parametrize("logn,B", [(1, 3), (2, 3), (3, 3), (4, 5), (5, 4), (6, 3), (7, 3),
+                                    (8, 3), (9, 3), (10, 3), (11, 2), (12, 3), (13, 2),
+                                    (14, 2), (15, 2), (16, 2)])
+def test_fixed_point_bit_exact(logn, B):
+    """Fixed point (QFT_I32): forward and adjoint bit-identical to the integer
+    oracle, on inputs within the overflow-free range and on full-range int32
+    inputs (wrapping); in range, close to the exact DFT."""
+    N = 1 << logn
+    say(f"fixed point: N=2^{logn} B={B}")
+    rng = np.random.default_rng(3300 + logn)
+    plan = qft.FixedPlan(logn, B)
+    for lim in (1 << (28 - logn), 1 << 31):
+        x = rng.integers(-lim, lim, (B, N, 2)).astype(np.int32)
+        xt = torch.from_numpy(x).to(DEV)
+        X = plan.forward(xt).cpu().numpy().astype(np.int64)
+        assert np.array_equal(X, _fixed_ref(x)), lim
+        Y = plan.adjoint(xt).cpu().numpy().astype(np.int64)
+        assert np.array_equal(Y, _fixed_ref(x[..., ::-1])[..., ::-1]), lim
+        if lim < (1 << 31):
+            exact = OB.cdft((x[..., 0] + 1j * x[..., 1]).astype(np.complex128))
+            err = D.relative_l2(X[..., 0] + 1j * X[..., 1], exact).max()
+            assert err < 1e-3, err
+    plan.close()
