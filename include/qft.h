@@ -166,7 +166,11 @@ qft_status qft_plan_info(qft_plan_t plan, int64_t* total_points, int64_t* algo_b
  * passes (every schedule of a plan gives bit-identical results).
  *  - Uniform plans, N <= 2^14: schedule 0 ("t<T>:<r>") is the kernel
  *    specialised for N, one workgroup per tile of 2^T = 2^max(10, r) cells;
- *    for batches of at most 2^20 transforms, "g<T>:<r>" for every T from
+ *    "t<T>:<r>/lds" the same with the constant table read from a copy in
+ *    LDS; for N = 2^13, 2^14 with more tiles than resident workgroups,
+ *    "t<T>:<r>/pipe" runs it on a resident grid whose workgroups load each
+ *    next tile while the current one runs; for batches of at most 2^20
+ *    transforms, "g<T>:<r>" for every T from
  *    max(10, r) to 14 runs the size-generic persistent kernel of uneven plans
  *    with tiles of 2^T cells over a transform list.
  *  - Uniform plans, N = 2^15, 2^16 (two-pass): "two-pass" (pass A as a
@@ -185,7 +189,8 @@ qft_status qft_plan_info(qft_plan_t plan, int64_t* total_points, int64_t* algo_b
  *    as one workgroup per tile ("/all"); names read "t<T>:<r range>+..".
  *    Schedule 0 runs every transform of up to 2^14 points in ONE persistent
  *    launch.  Longer transforms run after them with the default two-pass or
- *    multi-pass schedule.
+ *    multi-pass schedule, a run of same-size ones that lie back to back as
+ *    one batched exec (its workspace at most 2^22 cells per buffer).
  * A new plan starts on schedule 0, or on the schedule the autotuner chose for
  * a plan of the same shape on the same kind of device, if the schedule cache
  * holds one: a JSON file at $QFT_SCHEDULE_CACHE ("off" disables it), else

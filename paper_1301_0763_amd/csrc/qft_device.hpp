@@ -1722,28 +1722,59 @@ QFT_HD void mp_chain_combine_item(const IO& io, EP Ein, OP Wo, int logn, int p, 
   }
 }
 
-// Whole tile: T transforms of 2^LOGN points, NT threads (LOGN >= 1).
-template <int LOGN, int T, int NT, int WAVE, class Sync, class WSync, typename WP, class IO>
-QFT_HD void tile_body_s(const IO& io, WP W, int Tact, const float* sec, int tid, Sync sync,
-                        WSync wsync) {
-  constexpr int n = 1 << LOGN, h = n >> 1;
-  constexpr int total = T << (LOGN - 1);
-  constexpr int FI = total / NT;
-  static_assert(total % NT == 0, "fold items per thread");
-  const int tot_act = Tact << (LOGN - 1);
-  // Fold: item it of a thread is the pair (m, N - m) of transform t; the
-  // pair goes to heap cell (N >> (l + 2)) + (m >> (l + 1)), l = ctz(m), of
-  // both sides (m = 0: cells 0 and N/2).
-  typename IO::Raw raw[FI];
+// An opaque copy: the compiler must treat v as changed here (no instruction
+// is emitted on the GPU).
+QFT_HD void launder(int& v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(v));
+#else
+  (void)v;
+#endif
+}
+
+// Whole tile: T transforms of 2^LOGN points, NT threads (LOGN >= 1), in
+// three steps: tile_fetch_s loads a thread's fold items from x into
+// registers, tile_fold_s folds them into LDS, tile_rest_s runs the rounds,
+// the chain and the combine and writes X.  Fold item it of a thread is the
+// pair (m, N - m) of transform t; the pair goes to heap cell
+// (N >> (l + 2)) + (m >> (l + 1)), l = ctz(m), of both sides (m = 0: cells
+// 0 and N/2).  With h = N/2 >= NT, t = it NT / h and m = tid + (it NT mod h);
+// else every item of a thread has m = tid mod h and t steps by NT / h.
+template <int LOGN, int T, int NT>
+QFT_HD constexpr int tile_items() {
+  static_assert(((T << (LOGN - 1)) % NT) == 0, "fold items per thread");
+  return (T << (LOGN - 1)) / NT;
+}
+
+template <int LOGN, int T, int NT, class IO>
+QFT_HD void tile_fetch_s(const IO& io, int Tact, int tid,
+                         typename IO::Raw (&raw)[tile_items<LOGN, T, NT>()]) {
+  constexpr int h = (1 << LOGN) >> 1;
+  constexpr int FI = tile_items<LOGN, T, NT>();
   if constexpr (h >= NT) {
-    // t = it NT / h, m = tid + (it NT mod h): for tid != 0 the low bits of
-    // m, hence l, are tid's, and the cell is a per-thread base plus a
-    // constant shifted by l
 #pragma unroll
     for (int it = 0; it < FI; ++it) {
       const int t = (it * NT) / h;
       if (t < Tact) io.fetch(t, tid + (it * NT) % h, raw[it]);
     }
+  } else {
+    constexpr int TS = NT / h;
+    const int m = tid & (h - 1);
+    const int t0 = tid >> (LOGN - 1);
+#pragma unroll
+    for (int it = 0; it < FI; ++it)
+      if (t0 + it * TS < Tact) io.fetch(t0 + it * TS, m, raw[it]);
+  }
+}
+
+template <int LOGN, int T, int NT, typename WP, class IO>
+QFT_HD void tile_fold_s(const IO& io, WP W, int Tact, int tid,
+                        const typename IO::Raw (&raw)[tile_items<LOGN, T, NT>()]) {
+  constexpr int n = 1 << LOGN, h = n >> 1;
+  constexpr int FI = tile_items<LOGN, T, NT>();
+  if constexpr (h >= NT) {
+    // for tid != 0 the low bits of m, hence l, are tid's, and the cell is a
+    // per-thread base plus a constant shifted by l
     const int l = __builtin_ctz(tid | NT);
     const int cb = (n >> (l + 2)) + (tid >> (l + 1));
 #pragma unroll
@@ -1769,14 +1800,10 @@ QFT_HD void tile_body_s(const IO& io, WP W, int Tact, const float* sec, int tid,
       }
     }
   } else {
-    // every item of a thread has m = tid mod h; t steps by NT / h
     constexpr int TS = NT / h;
     static_assert((TS * n) % kRowCells == 0, "fold rows step by whole row units");
     const int m = tid & (h - 1);
     const int t0 = tid >> (LOGN - 1);
-#pragma unroll
-    for (int it = 0; it < FI; ++it)
-      if (t0 + it * TS < Tact) io.fetch(t0 + it * TS, m, raw[it]);
     int c1 = 0, c2 = h;
     if (m != 0) {
       const int l = __builtin_ctz(m);
@@ -1795,6 +1822,16 @@ QFT_HD void tile_body_s(const IO& io, WP W, int Tact, const float* sec, int tid,
       }
     }
   }
+}
+
+// Starts with a workgroup barrier (the fold's LDS stores); ends with the
+// combine's LDS reads, unordered.
+template <int LOGN, int T, int NT, int WAVE, class Sync, class WSync, typename WP, class IO>
+QFT_HD void tile_rest_s(const IO& io, WP W, int Tact, const float* sec, int tid, Sync sync,
+                        WSync wsync) {
+  constexpr int n = 1 << LOGN, h = n >> 1;
+  constexpr int FI = tile_items<LOGN, T, NT>();
+  const int tot_act = Tact << (LOGN - 1);
   sync();
   if constexpr (LOGN >= 3)
     sweeps_s<LOGN - 2, LOGN - 1, 2 * T, NT, WAVE, SIDES_ALT, true>(W, sec, tid, sync, wsync);
@@ -1818,6 +1855,53 @@ QFT_HD void tile_body_s(const IO& io, WP W, int Tact, const float* sec, int tid,
         io.put(Xt, n, k, w[k], w[h + k]);
       }
     }
+  }
+}
+
+template <int LOGN, int T, int NT, int WAVE, class Sync, class WSync, typename WP, class IO>
+QFT_HD void tile_body_s(const IO& io, WP W, int Tact, const float* sec, int tid, Sync sync,
+                        WSync wsync) {
+  typename IO::Raw raw[tile_items<LOGN, T, NT>()];
+  tile_fetch_s<LOGN, T, NT>(io, Tact, tid, raw);
+  tile_fold_s<LOGN, T, NT>(io, W, Tact, tid, raw);
+  tile_rest_s<LOGN, T, NT, WAVE>(io, W, Tact, sec, tid, sync, wsync);
+}
+
+// Persistent tiles of a contiguous batch: the workgroup takes tiles first,
+// first + stride, .. < ntiles (tile w: transforms [w T, w T + T) of the
+// batch, the last one ragged) and loads each next tile's x into registers
+// while the current one runs its rounds in LDS, so that the loads overlap
+// the LDS work.  The rounds must not read global memory (sec in LDS): the
+// vector memory counter is in order, and a read issued after the loads
+// would wait for them.
+// Before its first fold it calls pre() (the kernel's copy of the constant
+// table into LDS, issued behind the first tile's loads).
+template <int LOGN, int T, int NT, int WAVE, int DT, bool SWAP, class Sync, class WSync,
+          typename WP, class Pre>
+QFT_HD void tile_loop_s(const typename Store<DT>::T* x, typename Store<DT>::T* X,
+                        int64_t batch, int64_t first, int64_t stride, WP W, const float* sec,
+                        int tid, Sync sync, WSync wsync, Pre pre) {
+  using IO = ContigIO<DT, SWAP, LOGN>;
+  const int64_t ntiles = (batch + T - 1) / T;
+  if (first >= ntiles) return;
+  auto io_of = [&](int64_t w) { return IO(x + ((w * T) << LOGN), X + ((w * T) << LOGN)); };
+  auto count_of = [&](int64_t w) { return (int)(batch - w * T < T ? batch - w * T : T); };
+  typename IO::Raw raw[tile_items<LOGN, T, NT>()];
+  tile_fetch_s<LOGN, T, NT>(io_of(first), count_of(first), tid, raw);
+  pre();
+  for (int64_t w = first;;) {
+    // per tile, so that the compiler does not hold every thread-dependent
+    // LDS address of the bodies live across the loop
+    launder(tid);
+    const IO io = io_of(w);
+    const int cnt = count_of(w);
+    tile_fold_s<LOGN, T, NT>(io, W, cnt, tid, raw);
+    const int64_t wn = w + stride;
+    if (wn < ntiles) tile_fetch_s<LOGN, T, NT>(io_of(wn), count_of(wn), tid, raw);
+    tile_rest_s<LOGN, T, NT, WAVE>(io, W, cnt, sec, tid, sync, wsync);
+    if (wn >= ntiles) break;
+    sync();  // the combine's LDS reads before the next fold's stores
+    w = wn;
   }
 }
 
@@ -2099,16 +2183,6 @@ QFT_HD int tp_tile_segment(int64_t T) { return (int)((T >> 3) & 3); }
 QFT_HD int64_t tp_next_tile(int64_t T, int64_t stride, int64_t ntiles, int64_t batch) {
   while (T < ntiles && tp_tile_transform(T) >= batch) T += stride;
   return T;
-}
-
-// An opaque copy: the compiler must treat v as changed here (no instruction
-// is emitted on the GPU).
-QFT_HD void launder(int& v) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  asm volatile("" : "+v"(v));
-#else
-  (void)v;
-#endif
 }
 
 // Pass-A threads per workgroup for N = 2^16 (2^13-cell segments, 32 cells

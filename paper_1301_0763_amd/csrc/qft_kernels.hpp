@@ -55,7 +55,11 @@ constexpr int tile_wgs_per_cu(int tl) {
 // One tile-kernel launch.  Uniform groups (d_tiles == nullptr): a
 // contiguous batch of `ubatch` transforms of 2^ulog2n points in tiles of
 // T = 2^(tl - ulog2n) transforms (the last one ragged), one workgroup per
-// tile (tl = max(10, ulog2n)).  Uneven groups: tile w = (log2n, first,
+// tile (grid = ntiles) or, for one transform of 2^13 or 2^14 points per
+// tile, `grid` < ntiles resident workgroups striding over them and loading
+// each next tile during the current one (tl = max(10, ulog2n)); lds_sec:
+// the rounds read the constant table from a copy in LDS (always so on a
+// resident grid).  Uneven groups: tile w = (log2n, first,
 // count, 0) holds `count` transforms of 2^log2n points at element offsets
 // d_offs[first .. first + count); `grid` workgroups stride over the tiles
 // (grid = ntiles: one workgroup per tile) and exit after their last one.
@@ -68,6 +72,7 @@ struct TileGroup {
   int ulog2n;
   int64_t ubatch;
   int64_t rows;  // real-input plans: real signals (2 per transform slot)
+  bool lds_sec = false;
 };
 
 // Pointers of a real-input exec: rdft in0 -> out0; DCT-0/DST-0 in0 (c) ->

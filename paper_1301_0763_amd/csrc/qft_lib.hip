@@ -40,8 +40,8 @@ namespace qftk {
 
 // Two-pass path, N = 8 * 2^MC_LOG2.  Pass A: both sides of one segment per
 // workgroup, 4 tiles per transform (tp_tile_transform / tp_tile_segment put
-// the four on one XCD); a grid smaller than the tile count is persistent
-// and prefetches each next tile's x (tp_pass_a2_loop).
+// the four on one XCD); a grid smaller than the tile count is persistent,
+// its workgroups striding over the tiles (tp_pass_a2_loop).
 template <int MC_LOG2, int BLOCK, int DT, bool SWAP>
 __global__ __launch_bounds__(BLOCK) void tp_a2_kernel(const typename Store<DT>::T* x, float2* W,
                                                        int64_t batch, int64_t ntiles,
@@ -107,6 +107,9 @@ struct LargeItem {
   int64_t offset;
   int64_t batch;
 };
+// Most cells of one workspace buffer that an uneven plan spends on batching
+// a run of same-size long transforms (2^22 cells: 32 MiB).
+constexpr int64_t kLargeRunCells = (int64_t)1 << 22;
 
 // A schedule: tile-group launches, in order, for the transforms of N <= 2^14,
 // and how pass A of the two-pass path (N = 2^15, 2^16) covers its tiles.
@@ -239,7 +242,9 @@ void free_plan(qft_plan_s* p) {
 }
 
 qft_status alloc_common(qft_plan_s* p) {
-  const int lg = std::max(p->max_log2n, 3);
+  // at least the table of 2^14 points: the persistent tile kernel of 2^TL-cell
+  // tiles copies the first 2^TL / 4 floats into LDS whatever sizes it runs
+  const int lg = std::max(p->max_log2n, qftk::kMaxTileLog2);
   const int64_t nt = ((int64_t)1 << lg) / 4;
   std::vector<float> h(nt);
   qftk::fill_secants(h.data(), lg);
@@ -643,6 +648,20 @@ qft_status qft_plan_create(qft_plan_t* plan, int log2n, int64_t batch, qft_dtype
     sc.groups.resize(1);
     s = uniform_group(p, tl, &sc.groups[0]);
     if (s == QFT_SUCCESS) p->schedules.push_back(sc);
+    // the same with the constant table copied into LDS; and for one
+    // transform of 2^13 or 2^14 points per tile on a resident grid that
+    // loads each next tile during the current one, where there are more
+    // tiles than resident workgroups
+    if (s == QFT_SUCCESS) {
+      Schedule ls = sc;
+      ls.name += "/lds";
+      ls.groups[0].lds_sec = true;
+      p->schedules.push_back(ls);
+      Schedule pp = ls;
+      pp.name = sc.name + "/pipe";
+      pp.groups[0].grid = group_grid(p, tl, pp.groups[0].ntiles, true);
+      if (log2n >= 13 && pp.groups[0].grid < pp.groups[0].ntiles) p->schedules.push_back(pp);
+    }
     // the size-generic persistent kernel of uneven plans on a transform list,
     // tiles of 2^tl2 cells for every tl2 that holds a transform (batches of
     // at most 2^20 transforms: the list costs 8 bytes per transform)
@@ -724,10 +743,19 @@ qft_status qft_plan_create_uneven(qft_plan_t* plan, const int32_t* log2n, int64_
     if (log2n[i] > qftk::kMaxTileLog2) big.push_back(i);
   std::stable_sort(big.begin(), big.end(),
                    [&](int64_t a, int64_t b) { return log2n[a] > log2n[b]; });
-  for (int64_t i : big) {
-    p->large.push_back({log2n[i], off[i], 1});
-    p->work_cells = std::max<int64_t>(p->work_cells, (int64_t)1 << log2n[i]);
-    p->work_buffers = std::max(p->work_buffers, log2n[i] <= 16 ? 1 : 2);
+  // a run of same-size transforms that lie back to back in memory is one
+  // batched launch (its workspace at most kLargeRunCells per buffer)
+  for (size_t a = 0; a < big.size();) {
+    const int lg = log2n[big[a]];
+    const int64_t cap = std::max<int64_t>(1, kLargeRunCells >> lg);
+    int64_t k = 1;
+    while (a + k < big.size() && k < cap && log2n[big[a + k]] == lg &&
+           off[big[a + k]] == off[big[a]] + (k << lg))
+      ++k;
+    p->large.push_back({lg, off[big[a]], k});
+    p->work_cells = std::max<int64_t>(p->work_cells, k << lg);
+    p->work_buffers = std::max(p->work_buffers, lg <= 16 ? 1 : 2);
+    a += (size_t)k;
   }
   if (!big.empty()) set_tp_resident(p);
   // Candidate schedules: tile size for N <= 2^10, 2^11, 2^12, 2^13 and 2^14;

@@ -7,6 +7,10 @@
 //
 //  * tile_kernel_u: a contiguous batch of one size, one workgroup per tile,
 //    for every N with max(2^12, N) = 2^TL (uniform plans);
+//    with the constant table read from global memory or from a copy in LDS;
+//  * tile_kernel_p: one transform of 2^13 or 2^14 points per tile on a
+//    resident grid, each workgroup loading its next tile's x while the
+//    current one runs;
 //  * tile_kernel_g: the persistent kernel of uneven plans; a workgroup takes
 //    tiles w = blockIdx.x, blockIdx.x + gridDim.x, ... of a size-sorted list
 //    and runs the compile-time specialised body of each tile's size.
@@ -20,19 +24,74 @@
 
 namespace qftk {
 
-template <int LOGN, int TL, int DT, bool SWAP>
+// The constant table of transforms up to 2^LOGN points (its first 2^LOGN / 4
+// floats, Sec. 6.1) copied into LDS, where the rounds read their secants
+// (the LDS reads are cheaper than table reads through the vector memory
+// path, whose in-order counter would also make them wait for any input
+// loads in flight).  Issued after the tile's x loads, so that the wait for
+// the table is the wait for x that the fold has anyway; the fold's
+// workgroup barrier orders the copy before the first read.
+template <int LOGN>
+constexpr int lds_secants() {
+  return LOGN >= 3 ? (1 << LOGN) / 4 : 1;
+}
+template <int LOGN, int NT>
+__device__ __forceinline__ void secants_to_lds(float* sl, const float* __restrict__ sec,
+                                               int tid) {
+  if constexpr (LOGN >= 3) {
+#pragma unroll
+    for (int i = tid; i < lds_secants<LOGN>(); i += NT) sl[i] = sec[i];
+  }
+}
+
+// LSEC: the rounds read the constant table from a copy in LDS, else from
+// global memory (which is faster depends on the size and the batch).
+template <int LOGN, int TL, int DT, bool SWAP, bool LSEC>
 __global__ __launch_bounds__(tile_threads_one(LOGN, TL)) void tile_kernel_u(const typename Store<DT>::T* x,
                                                                    typename Store<DT>::T* X,
                                                                    int64_t batch,
                                                                    const float* sec) {
   constexpr int T = 1 << (TL - LOGN);
+  constexpr int NT = tile_threads_one(LOGN, TL);
   __shared__ float2 Wl[padded_cells<kPad>(1 << TL)];
   const PadPtr<kPad> W{Wl, 0};
+  const int tid = (int)threadIdx.x;
   const int64_t t0 = (int64_t)blockIdx.x * T;
   const int count = (int)min((int64_t)T, batch - t0);
   const ContigIO<DT, SWAP, LOGN> io(x + (t0 << LOGN), X + (t0 << LOGN));
-  tile_body_s<LOGN, T, tile_threads_one(LOGN, TL), kWave>(io, W, count, sec, (int)threadIdx.x,
-                                                          DevSync{}, DevWaveSync{});
+  if constexpr (LSEC) {
+    __shared__ float Sl[lds_secants<LOGN>()];
+    typename ContigIO<DT, SWAP, LOGN>::Raw raw[tile_items<LOGN, T, NT>()];
+    tile_fetch_s<LOGN, T, NT>(io, count, tid, raw);
+    secants_to_lds<LOGN, NT>(Sl, sec, tid);
+    tile_fold_s<LOGN, T, NT>(io, W, count, tid, raw);
+    tile_rest_s<LOGN, T, NT, kWave>(io, W, count, Sl, tid, DevSync{}, DevWaveSync{});
+  } else {
+    tile_body_s<LOGN, T, NT, kWave>(io, W, count, sec, tid, DevSync{}, DevWaveSync{});
+  }
+}
+
+// The same tiles on a resident grid: workgroup b takes tiles b, b + gridDim.x,
+// .. and loads each next tile's x while the current one runs (tile_loop_s);
+// built for one transform of 2^13 or 2^14 points per tile, the sizes whose
+// LDS leaves room for only one or two workgroups per CU (with more, the
+// workgroups of a CU already overlap one another's loads, and a resident
+// grid measured slower).
+template <int LOGN, int TL, int DT, bool SWAP>
+__global__ __launch_bounds__(tile_threads_one(LOGN, TL)) void tile_kernel_p(const typename Store<DT>::T* x,
+                                                                   typename Store<DT>::T* X,
+                                                                   int64_t batch,
+                                                                   const float* sec) {
+  constexpr int T = 1 << (TL - LOGN);
+  constexpr int NT = tile_threads_one(LOGN, TL);
+  __shared__ float2 Wl[padded_cells<kPad>(1 << TL)];
+  __shared__ float Sl[lds_secants<LOGN>()];
+  const PadPtr<kPad> W{Wl, 0};
+  const int tid = (int)threadIdx.x;
+  tile_loop_s<LOGN, T, NT, kWave, DT, SWAP>(x, X, batch, (int64_t)blockIdx.x,
+                                            (int64_t)gridDim.x, W, Sl, tid, DevSync{},
+                                            DevWaveSync{},
+                                            [&]() { secants_to_lds<LOGN, NT>(Sl, sec, tid); });
 }
 
 template <int TL, int DT, bool SWAP, int LOGN>
@@ -55,7 +114,9 @@ __global__ __launch_bounds__(tile_threads(TL), 4) void tile_kernel_g(
     const typename Store<DT>::T* x, typename Store<DT>::T* X, const int4* __restrict__ tiles,
     const int64_t* __restrict__ offs, int ntiles, const float* sec) {
   __shared__ float2 Wl[padded_cells<kPad>(1 << TL)];
+  __shared__ float Sl[lds_secants<TL>()];
   const PadPtr<kPad> W{Wl, 0};
+  secants_to_lds<TL, tile_threads(TL)>(Sl, sec, (int)threadIdx.x);
   for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
     // the descriptor is the same for the whole workgroup: broadcast it from
     // lane 0, so that the size dispatch below is a uniform (scalar) branch
@@ -68,7 +129,7 @@ __global__ __launch_bounds__(tile_threads(TL), 4) void tile_kernel_g(
     // loop and keeps them all live (hundreds of registers, spills).
     int tid = (int)threadIdx.x;
     __asm__ volatile("" : "+v"(tid));
-    tile_switch<TL, DT, SWAP, 1>(logn, io, W, count, sec, tid);
+    tile_switch<TL, DT, SWAP, 1>(logn, io, W, count, Sl, tid);
     __syncthreads();
   }
 }
@@ -139,9 +200,22 @@ hipError_t launch_uniform(const TileGroup& g, const void* in, void* out, const f
   if constexpr (LOGN <= TL) {
     if (g.ulog2n != LOGN) return launch_uniform<DT, TL, SWAP, LOGN + 1>(g, in, out, sec, st);
     if constexpr ((LOGN < kMinTileLog2 ? kMinTileLog2 : LOGN) == TL) {
-      hipLaunchKernelGGL((tile_kernel_u<LOGN, TL, DT, SWAP>), dim3((unsigned)g.ntiles),
-                         dim3(tile_threads_one(LOGN, TL)), 0, st, (const E*)in, (E*)out,
-                         g.ubatch, sec);
+      if (g.grid < g.ntiles) {
+        if constexpr (LOGN == TL && TL >= 13)
+          hipLaunchKernelGGL((tile_kernel_p<LOGN, TL, DT, SWAP>), dim3((unsigned)g.grid),
+                             dim3(tile_threads_one(LOGN, TL)), 0, st, (const E*)in, (E*)out,
+                             g.ubatch, sec);
+        else
+          return hipErrorInvalidValue;
+      } else if (g.lds_sec) {
+        hipLaunchKernelGGL((tile_kernel_u<LOGN, TL, DT, SWAP, true>), dim3((unsigned)g.ntiles),
+                           dim3(tile_threads_one(LOGN, TL)), 0, st, (const E*)in, (E*)out,
+                           g.ubatch, sec);
+      } else {
+        hipLaunchKernelGGL((tile_kernel_u<LOGN, TL, DT, SWAP, false>), dim3((unsigned)g.ntiles),
+                           dim3(tile_threads_one(LOGN, TL)), 0, st, (const E*)in, (E*)out,
+                           g.ubatch, sec);
+      }
       return hipGetLastError();
     }
   }

@@ -269,6 +269,31 @@ int tile_s_run(const void* x, void* X, int Tact, const float* sec, const int64_t
   return tr.oob ? -100 : (int)tr.races;
 }
 
+// The resident-grid tile kernel: `grid` workgroups, workgroup b taking tiles
+// b, b + grid, .. of a contiguous batch and loading each next tile's x while
+// the current one runs (tile_loop_s), with the GPU's tile size and threads.
+template <int DT, bool SWAP, int LOGN>
+int tile_p_impl(const void* x, void* X, int64_t batch, int64_t grid, const float* sec) {
+  using E = typename qftk::Store<DT>::T;
+  constexpr int TL = LOGN <= 10 ? 10 : LOGN;
+  constexpr int NT = emu_tile_threads<LOGN, TL>(false);
+  constexpr int T = 1 << (TL - LOGN);
+  const int64_t cells = (int64_t)T << LOGN;
+  int64_t races = 0;
+  for (int64_t b = 0; b < grid; ++b) {
+    std::vector<float2> lds(cells + (cells >> kEmuPad));
+    Tracker tr(NT);
+    TPtr W{lds.data(), 0, &tr, cells, kEmuPad};
+    run_workgroup(NT, tr, [&](int tid, auto sync, auto wsync) {
+      qftk::tile_loop_s<LOGN, T, NT, 64, DT, SWAP>((const E*)x, (E*)X, batch, b, grid, W, sec,
+                                                  tid, sync, wsync, []() {});
+    });
+    if (tr.oob) return -100;
+    races += tr.races;
+  }
+  return (int)races;
+}
+
 template <int DT, bool SWAP, int LOGN>
 int tile_s_impl(const void* x, void* X, int Tact, const float* sec, const int64_t* offs) {
   constexpr int TL = LOGN <= 10 ? 10 : LOGN;
@@ -336,6 +361,28 @@ int tile_s_dispatch(const void* x, void* X, int logn, int Tact, const float* sec
     case 12: return tile_s_impl<DT, SWAP, 12>(x, X, Tact, sec, offs);
     case 13: return tile_s_impl<DT, SWAP, 13>(x, X, Tact, sec, offs);
     case 14: return tile_s_impl<DT, SWAP, 14>(x, X, Tact, sec, offs);
+    default: return -1;
+  }
+}
+
+template <int DT, bool SWAP>
+int tile_p_dispatch(const void* x, void* X, int logn, int64_t batch, int64_t grid,
+                    const float* sec) {
+  switch (logn) {
+    case 1: return tile_p_impl<DT, SWAP, 1>(x, X, batch, grid, sec);
+    case 2: return tile_p_impl<DT, SWAP, 2>(x, X, batch, grid, sec);
+    case 3: return tile_p_impl<DT, SWAP, 3>(x, X, batch, grid, sec);
+    case 4: return tile_p_impl<DT, SWAP, 4>(x, X, batch, grid, sec);
+    case 5: return tile_p_impl<DT, SWAP, 5>(x, X, batch, grid, sec);
+    case 6: return tile_p_impl<DT, SWAP, 6>(x, X, batch, grid, sec);
+    case 7: return tile_p_impl<DT, SWAP, 7>(x, X, batch, grid, sec);
+    case 8: return tile_p_impl<DT, SWAP, 8>(x, X, batch, grid, sec);
+    case 9: return tile_p_impl<DT, SWAP, 9>(x, X, batch, grid, sec);
+    case 10: return tile_p_impl<DT, SWAP, 10>(x, X, batch, grid, sec);
+    case 11: return tile_p_impl<DT, SWAP, 11>(x, X, batch, grid, sec);
+    case 12: return tile_p_impl<DT, SWAP, 12>(x, X, batch, grid, sec);
+    case 13: return tile_p_impl<DT, SWAP, 13>(x, X, batch, grid, sec);
+    case 14: return tile_p_impl<DT, SWAP, 14>(x, X, batch, grid, sec);
     default: return -1;
   }
 }
@@ -672,6 +719,17 @@ int emu_tile_s(int dt, int swap, const void* x, void* X, int logn, int Tact,
                            : tile_s_dispatch<0, false>(x, X, logn, Tact, sec.data(), offs);
   return swap ? tile_s_dispatch<1, true>(x, X, logn, Tact, sec.data(), offs)
               : tile_s_dispatch<1, false>(x, X, logn, Tact, sec.data(), offs);
+}
+
+// The resident-grid tile kernel (tile_kernel_p) with `grid` workgroups.
+int emu_tile_p(int dt, int swap, const void* x, void* X, int logn, int64_t batch,
+               int64_t grid) {
+  if (batch < 1 || grid < 1) return -1;
+  std::vector<float> sec = secants(logn < 3 ? 3 : logn);
+  if (dt == 0) return swap ? tile_p_dispatch<0, true>(x, X, logn, batch, grid, sec.data())
+                           : tile_p_dispatch<0, false>(x, X, logn, batch, grid, sec.data());
+  return swap ? tile_p_dispatch<1, true>(x, X, logn, batch, grid, sec.data())
+              : tile_p_dispatch<1, false>(x, X, logn, batch, grid, sec.data());
 }
 
 // One workgroup of the real-input tile kernel (kind 0: rdft in0 -> out0;

@@ -173,9 +173,8 @@ def test_multipass_level_splits_agree(emu, logn, seg):
 @pytest.mark.parametrize("grid", [32, 64])
 def test_two_pass_persistent(emu, mc_log2, batch, grid):
     """Persistent pass A (a grid of whole groups of 32 workgroups, each taking
-    every grid-th tile and loading the next tile's x while the current one
-    runs): bit-identical to one workgroup per tile, on batches whose last
-    group of eight transforms is ragged, and race free."""
+    every grid-th tile): bit-identical to one workgroup per tile, on batches
+    whose last group of eight transforms is ragged, and race free."""
     logn = mc_log2 + 3
     x = workloads.normal(600 + mc_log2, (batch, 1 << logn))
     r0, ref = run_tp(emu, x, mc_log2)
@@ -196,6 +195,35 @@ def test_two_pass_library_size(emu):
         assert D.relative_l2(out, _ref(x)).max() <= _tol(mc + 3)
         races, pout = run_tp(emu, x, mc, grid=32)
         assert races == 0 and np.array_equal(pout, out)
+
+
+@pytest.mark.parametrize("logn,batch,grid", [(1, 1100, 2), (4, 200, 3), (7, 19, 2), (10, 5, 2),
+                                             (11, 7, 3), (12, 5, 2), (13, 3, 2), (14, 3, 2)])
+@pytest.mark.parametrize("swap", [0, 1])
+def test_resident_grid_tiles(emu, logn, batch, grid, swap):
+    """The resident-grid tile kernel (each workgroup strides over the tiles
+    and loads its next tile's x while the current one runs its rounds):
+    bit-identical to one workgroup per tile, with several tiles per
+    workgroup, a ragged last tile and workgroups without one; race free."""
+    N = 1 << logn
+    T = max(1, 1024 // N)
+    x = _as_c64(workloads.uniform(900 + logn, (batch, N)))
+    ref = np.zeros_like(x)
+    for t0 in range(0, batch, T):
+        cnt = min(T, batch - t0)
+        sub = np.ascontiguousarray(x[t0:t0 + cnt])
+        o = np.zeros_like(sub)
+        assert emu.emu_tile_s(0, swap, sub.ctypes.data, o.ctypes.data, logn, cnt, None) == 0
+        ref[t0:t0 + cnt] = o
+    out = np.zeros_like(x)
+    assert emu.emu_tile_p(0, swap, x.ctypes.data, out.ctypes.data, logn, batch, grid) == 0
+    assert np.array_equal(out, ref)
+    # more workgroups than tiles: the extra ones exit at once
+    ntiles = -(-batch // T)
+    out2 = np.zeros_like(x)
+    assert emu.emu_tile_p(0, swap, x.ctypes.data, out2.ctypes.data, logn, batch,
+                          ntiles + 1) == 0
+    assert np.array_equal(out2, ref)
 
 
 @pytest.mark.parametrize("logn", range(1, 15))

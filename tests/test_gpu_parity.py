@@ -521,6 +521,27 @@ def test_uneven_with_long_transforms():
     plan.close()
 
 
+def test_uneven_runs_of_long_transforms():
+    """Runs of same-size long transforms that lie back to back (2^15, 2^16,
+    2^17; the 2^16 run longer than one batched launch holds, 2^22 cells)
+    run as batched execs: every transform matches the oracle, forward and
+    adjoint."""
+    sizes = [15, 15, 15, 16, 16, 12] + [16] * 66 + [17, 17, 9, 15]
+    say(f"uneven runs of long transforms: {len(sizes)} transforms")
+    off = np.concatenate([[0], np.cumsum([1 << s for s in sizes])])
+    vals = workloads.normal(4322, (int(off[-1]),))
+    plan = qft.UnevenPlan(sizes)
+    xt = torch.from_numpy(vals).to(DEV)
+    got_f = plan.forward(xt).cpu().numpy()
+    got_b = plan.adjoint(xt).cpu().numpy()
+    for i, lg in enumerate(sizes):
+        seg = vals[off[i]:off[i + 1]].astype(np.complex128)[None]
+        check(got_f[off[i]:off[i + 1]][None], OB.cdft(seg), lg, what=f"run #{i} 2^{lg}")
+        check(got_b[off[i]:off[i + 1]][None], np.conj(OB.cdft(np.conj(seg))), lg,
+              what=f"run adjoint #{i} 2^{lg}")
+    plan.close()
+
+
 def test_two_streams_share_no_scratch():
     """fft() on two streams at once with the same shape (N = 2^16, a plan
     with scratch memory): each stream gets a plan of its own, and both results
@@ -542,11 +563,17 @@ def test_two_streams_share_no_scratch():
     check(outs["b"].cpu().numpy(), OB.cdft(xb.astype(np.complex128)), 16, what="stream b")
 
 
-@pytest.mark.parametrize("logn,B", [(18, 2), (12, 64)])
+@pytest.mark.parametrize("logn,B", [(18, 2), (12, 64), (12, 1500), (14, 300), (9, 9000),
+                                    (15, 300), (16, 260)])
 def test_stage_schedules_agree_and_autotune_is_cached(logn, B, tmp_path, monkeypatch):
     """A uniform plan's schedules (multi-pass: splits of the global passes;
-    tile sizes: the specialised kernel and the size-generic persistent kernel
-    with each tile size) give bit-identical results; autotune keeps the
+    tile sizes: the specialised kernel, one workgroup per tile and, where
+    there are more tiles than resident workgroups, on a resident grid that
+    loads each next tile during the current one, and the size-generic
+    persistent kernel with each tile size; two-pass: pass A as a persistent
+    grid, at these batches smaller than the tile count, and one workgroup
+    per tile) give
+    bit-identical results; autotune keeps the
     fastest and records it in the schedule cache, and a new plan of the same
     shape starts on the cached schedule (also one written by hand)."""
     cache = tmp_path / "schedules.json"
