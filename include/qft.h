@@ -179,7 +179,9 @@ qft_status qft_plan_info(qft_plan_t plan, int64_t* total_points, int64_t* algo_b
  *  - Uniform plans, N > 2^16 (multi-pass): "multi-pass:f,b,c", the most
  *    forward rounds, backward rounds and chain levels per global pass, for
  *    (f,b,c) in (4,5,5) (the default), (3,5,5), (4,4,5), (4,5,4), (3,4,4),
- *    (5,5,5).
+ *    (5,5,5), with LDS segments of 2^12 cells, and the same six with
+ *    segments of 2^13 cells ("multi-pass:f,b,c/s13": one round and one chain
+ *    level fewer in the global passes).
  *  - Uneven plans: which tile size serves each transform size of up to 2^14
  *    points, tiles of 2^10 .. 2^14 cells; the assignments for
  *    N <= 2^10, 2^11, 2^12, 2^13, 2^14 of {14,14,14,14,14}, {13,13,13,13,14},

@@ -102,12 +102,14 @@ hipError_t launch_real(const TileGroup& g, int kind, const RealArgs& a, const fl
 // DT): `batch` contiguous transforms of 2^log2n points, kMpSegLog2 + 3 <=
 // log2n <= 24 (swap: the adjoint), or `rows` real signals of a real-input
 // plan (kind as in launch_real; two signals per transform slot).  W0 and
-// W1 are heap buffers of (transforms or slots) * 2^log2n cells each.
-constexpr int kMpSegLog2 = 12;  // LDS segment of the multi-pass path
+// W1 are heap buffers of (transforms or slots) * 2^log2n cells each.  `seg`:
+// log2 of the LDS segment, 12 or 13 (log2n >= seg + 3); real-input plans use
+// kMpSegLog2.
+constexpr int kMpSegLog2 = 12;  // default LDS segment of the multi-pass path
 
 template <int DT>
 hipError_t launch_multipass(bool swap, const void* in, void* out, int log2n, int64_t batch,
-                            const float* sec, float2* W0, float2* W1, MpLevels lv,
+                            const float* sec, float2* W0, float2* W1, MpLevels lv, int seg,
                             hipStream_t st);
 
 template <int DT>

@@ -118,6 +118,7 @@ struct Schedule {
   std::vector<qftk::TileGroup> groups;
   bool tp_persistent = true;  // two-pass pass A: resident grid, else one workgroup per tile
   qftk::MpLevels mp{};        // multi-pass: most rounds / levels per global pass
+  int mp_seg = qftk::kMpSegLog2;  // multi-pass: log2 of the LDS segment
 };
 
 }  // namespace
@@ -346,7 +347,7 @@ qft_status launch_large(const qft_plan_s* p, const Schedule& s, const void* in, 
     return launch_twopass<DT, SWAP>(in, out, log2n, batch, sec, W0,
                                     s.tp_persistent ? p->tp_resident[log2n - 15] : 0, st);
   const hipError_t e =
-      qftk::launch_multipass<DT>(SWAP, in, out, log2n, batch, sec, W0, W1, s.mp, st);
+      qftk::launch_multipass<DT>(SWAP, in, out, log2n, batch, sec, W0, W1, s.mp, s.mp_seg, st);
   return e == hipSuccess ? QFT_SUCCESS : hip_fail(e);
 }
 
@@ -686,13 +687,19 @@ qft_status qft_plan_create(qft_plan_t* plan, int log2n, int64_t batch, qft_dtype
       p->schedules.push_back(Schedule{"two-pass/all", {}, false, {}});
     } else {
       // splits of the global passes: most forward rounds / backward rounds /
-      // chain levels per pass; the first is the default
+      // chain levels per pass, with LDS segments of 2^12 cells and, as
+      // "/s13", of 2^13 (one round and one chain level fewer in the global
+      // passes, one workgroup per CU in the segment pass); the first is the
+      // default
       const int splits[][3] = {{4, 5, 5}, {3, 5, 5}, {4, 4, 5}, {4, 5, 4}, {3, 4, 4}, {5, 5, 5}};
-      for (const auto& sp : splits) {
-        Schedule m{"multi-pass:" + std::to_string(sp[0]) + "," + std::to_string(sp[1]) + "," +
-                       std::to_string(sp[2]),
-                   {}, true, qftk::MpLevels{sp[0], sp[1], sp[2]}};
-        p->schedules.push_back(m);
+      for (const int seg : {12, 13}) {
+        if (log2n < seg + 3) continue;
+        for (const auto& sp : splits) {
+          Schedule m{"multi-pass:" + std::to_string(sp[0]) + "," + std::to_string(sp[1]) + "," +
+                         std::to_string(sp[2]) + (seg == 13 ? "/s13" : ""),
+                     {}, true, qftk::MpLevels{sp[0], sp[1], sp[2]}, seg};
+          p->schedules.push_back(m);
+        }
       }
     }
     set_tp_resident(p);

@@ -6,10 +6,11 @@
 //   fold        x -> heap (through the plan's IO accessor)
 //   fwd         up to 4 forward rounds of the large blocks per pass, in
 //               registers, in place
-//   segment     one workgroup per 2^12-cell segment index: the segment of
-//               both sides, its remaining forward and its backward rounds in
-//               LDS; workgroup 0 of a transform takes both side heads and
-//               also runs the chain to P = 2^13
+//   segment     one workgroup per segment index (2^12 or 2^13 cells, a
+//               schedule's choice): the segment of both sides, its remaining
+//               forward and its backward rounds in LDS; workgroup 0 of a
+//               transform takes both side heads and also runs the chain to
+//               twice the segment
 //   bwd         up to 5 backward rounds per pass, heap -> other buffer
 //   chain       up to 5 chain levels per pass, E values and outputs in the
 //               chain buffer, DCT-II / DST-II blocks read from the heap
@@ -92,8 +93,6 @@ __global__ __launch_bounds__(BLOCK) void mp_segment_kernel(float2* W, int logn,
 
 namespace {
 
-constexpr int kMpSegThreads = (2 << kMpSegLog2) / 32;
-
 unsigned grid_for(int64_t work) {
   int64_t g = (work + MP_BLOCK - 1) / MP_BLOCK;
   const int64_t cap = 1 << 20;
@@ -112,6 +111,7 @@ struct GpuMultipass {
   const float* sec;
   float2* cur;  // heap buffer
   float2* oth;  // the other buffer (backward output, then chain buffer)
+  int seg;      // log2 of the LDS segment (12 or 13)
   hipStream_t st;
   hipError_t err = hipSuccess;
 
@@ -135,9 +135,13 @@ struct GpuMultipass {
     }
   }
   void segment() {
-    const int64_t blocks = batch << (logn - 1 - kMpSegLog2);
-    hipLaunchKernelGGL((mp_segment_kernel<kMpSegLog2, kMpSegThreads>), dim3((unsigned)blocks),
-                       dim3(kMpSegThreads), 0, st, cur, logn, sec);
+    const int64_t blocks = batch << (logn - 1 - seg);
+    if (seg == 13)
+      hipLaunchKernelGGL((mp_segment_kernel<13, 512>), dim3((unsigned)blocks), dim3(512), 0, st,
+                         cur, logn, sec);
+    else
+      hipLaunchKernelGGL((mp_segment_kernel<12, 256>), dim3((unsigned)blocks), dim3(256), 0, st,
+                         cur, logn, sec);
   }
   template <int K>
   void bwd_k(int hi) {
@@ -196,17 +200,18 @@ struct GpuMultipass {
 };
 
 // `lv`: most forward rounds, backward rounds and chain levels per global
-// pass (1 .. 5 each; a plan's schedules offer several splits).
+// pass (1 .. 5 each; a plan's schedules offer several splits); `seg`: log2
+// of the LDS segment, 12 or 13.
 template <class IO>
 hipError_t run_multipass(const IO& io, int log2n, int64_t batch, const float* sec, float2* W0,
-                         float2* W1, MpLevels lv, hipStream_t st) {
-  if (log2n < kMpSegLog2 + 3 || log2n > 24 || batch < 1 ||
-      (batch << (log2n - 1 - kMpSegLog2)) > 0x7fffffff)
+                         float2* W1, MpLevels lv, int seg, hipStream_t st) {
+  if ((seg != 12 && seg != 13) || log2n < seg + 3 || log2n > 24 || batch < 1 ||
+      (batch << (log2n - 1 - seg)) > 0x7fffffff)
     return hipErrorInvalidValue;
   if (lv.fwd < 1 || lv.fwd > 5 || lv.bwd < 1 || lv.bwd > 5 || lv.chain < 1 || lv.chain > 5)
     return hipErrorInvalidValue;
-  GpuMultipass<IO> ex{io, log2n, batch, sec, W0, W1, st};
-  multipass_schedule(ex, log2n, kMpSegLog2, lv);
+  GpuMultipass<IO> ex{io, log2n, batch, sec, W0, W1, seg, st};
+  multipass_schedule(ex, log2n, seg, lv);
   if (ex.err != hipSuccess) return ex.err;
   return hipGetLastError();
 }
@@ -215,14 +220,14 @@ hipError_t run_multipass(const IO& io, int log2n, int64_t batch, const float* se
 
 template <int DT>
 hipError_t launch_multipass(bool swap, const void* in, void* out, int log2n, int64_t batch,
-                            const float* sec, float2* W0, float2* W1, MpLevels lv,
+                            const float* sec, float2* W0, float2* W1, MpLevels lv, int seg,
                             hipStream_t st) {
   using E = typename Store<DT>::T;
   if (swap)
     return run_multipass(ContigRtIO<DT, true>((const E*)in, (E*)out, log2n), log2n, batch, sec,
-                         W0, W1, lv, st);
+                         W0, W1, lv, seg, st);
   return run_multipass(ContigRtIO<DT, false>((const E*)in, (E*)out, log2n), log2n, batch, sec,
-                       W0, W1, lv, st);
+                       W0, W1, lv, seg, st);
 }
 
 template <int DT>
@@ -233,15 +238,15 @@ hipError_t launch_multipass_real(int kind, const RealArgs& a, int log2n, int64_t
   const int64_t slots = (rows + 1) / 2;
   if (kind == 0)
     return run_multipass(RealPairIO<DT, 0>{(const R*)a.in0, (E*)a.out0, rows, log2n}, log2n,
-                         slots, sec, W0, W1, MpLevels{}, st);
+                         slots, sec, W0, W1, MpLevels{}, kMpSegLog2, st);
   return run_multipass(DctDstIO<DT, 0>{(const R*)a.in0, (const R*)a.in1, (R*)a.out0,
                                        (R*)a.out1, rows, log2n},
-                       log2n, slots, sec, W0, W1, MpLevels{}, st);
+                       log2n, slots, sec, W0, W1, MpLevels{}, kMpSegLog2, st);
 }
 
 template hipError_t launch_multipass<QFT_MP_DT>(bool, const void*, void*, int, int64_t,
                                                 const float*, float2*, float2*, MpLevels,
-                                                hipStream_t);
+                                                int, hipStream_t);
 template hipError_t launch_multipass_real<QFT_MP_DT>(int, const RealArgs&, int, int64_t,
                                                      const float*, float2*, float2*,
                                                      hipStream_t);

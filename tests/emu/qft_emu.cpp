@@ -439,7 +439,8 @@ struct EmuMultipass {
   }
   template <int MC_LOG2>
   void segment_mc() {
-    // the GPU's 32 cells per thread for 2^12-cell segments, else <= 32 threads
+    // the GPU's 32 cells per thread for 2^12- and 2^13-cell segments, else
+    // <= 32 threads
     constexpr int MC = 1 << MC_LOG2;
     constexpr int NT = MC_LOG2 >= 12 ? (2 * MC) / 32 : (MC < 32 ? MC : 32);
     const int segs = 1 << (logn - 1 - MC_LOG2);
@@ -467,6 +468,7 @@ struct EmuMultipass {
       case 8: segment_mc<8>(); break;
       case 10: segment_mc<10>(); break;
       case 12: segment_mc<12>(); break;
+      case 13: segment_mc<13>(); break;
       default: races = -1000000; break;
     }
   }

@@ -94,11 +94,19 @@ def test_multipass_adjoint(emu):
 
 @pytest.mark.slow
 def test_multipass_library_segment_size(emu):
-    """N = 2^15 with the library's own 2^12-cell segments."""
+    """N = 2^15 with the library's 2^12-cell segments, and N = 2^16 with its
+    2^13-cell ones (the "/s13" schedules) bit-identical to 2^12-cell ones."""
     x = workloads.normal(15, (1, 1 << 15))
     races, out = run_mp(emu, x, 12, nthr=64)
     assert races == 0
     assert D.relative_l2(out, _ref(x)).max() <= _tol(15)
+    x = workloads.normal(16, (1, 1 << 16))
+    races, out12 = run_mp(emu, x, 12, nthr=64)
+    assert races == 0
+    races, out13 = run_mp(emu, x, 13, nthr=64)
+    assert races == 0
+    assert np.array_equal(out12, out13)
+    assert D.relative_l2(out13, _ref(x)).max() <= _tol(16)
 
 
 def test_uneven_worklist(emu):
