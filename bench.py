@@ -115,6 +115,16 @@ def extra_workloads(dev, stream):
         qft.qft_exec_bwd(plan.handle, y.data_ptr(), g.data_ptr(), cs)
     fb_graph_ms = time_ms(fb_graph.replay, stream, 20, 3)
     del fb_graph
+    # the same pair ten times in one graph: a replay's own launch cost
+    # spread over ten pairs
+    fb_graph10 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(fb_graph10):
+        cs = torch.cuda.current_stream().cuda_stream
+        for _ in range(10):
+            qft.qft_exec_fwd(plan.handle, xt.data_ptr(), y.data_ptr(), cs)
+            qft.qft_exec_bwd(plan.handle, y.data_ptr(), g.data_ptr(), cs)
+    fb_graph10_ms = time_ms(fb_graph10.replay, stream, 5, 1) / 10
+    del fb_graph10
     Xr = OB.cdft(x.astype(np.complex128))
     gref = 2 * np.conj(OB.cdft(np.conj(w * Xr)))
     bytes_dir = 2 * xt.numel() * 8
@@ -124,6 +134,7 @@ def extra_workloads(dev, stream):
         "fwd_GBps": round(bytes_dir / (fwd * 1e-3) / 1e9, 1),
         "bwd_GBps": round(bytes_dir / (bwd * 1e-3) / 1e9, 1),
         "fwd_plus_bwd_graph_replay_ms": round(fb_graph_ms, 5),
+        "fwd_plus_bwd_in_10_pair_graph_ms": round(fb_graph10_ms, 5),
         "autograd_step_ms": round(step, 5),
         "grad_rel_l2_max": float(f"{D.relative_l2(grad, gref).max():.3e}"),
     }
@@ -154,7 +165,13 @@ def extra_workloads(dev, stream):
     torch.cuda.synchronize()
     gms = time_ms(graph.replay, stream, 20, 3)
     graph_equal = bool(torch.equal(uo, eager))
-    del graph, eager
+    graph10 = torch.cuda.CUDAGraph()  # ten execs in one graph
+    with torch.cuda.graph(graph10):
+        for _ in range(10):
+            qft.qft_exec_fwd(up.handle, ut.data_ptr(), uo.data_ptr(),
+                             torch.cuda.current_stream().cuda_stream)
+    g10ms = time_ms(graph10.replay, stream, 5, 1) / 10
+    del graph, graph10, eager
     h16 = torch.from_numpy(np.stack([vals.real, vals.imag], -1).astype(np.float16)).to(dev)
     u16 = h16.view(torch.complex32).reshape(-1)
     o16 = torch.empty_like(u16)
@@ -170,6 +187,7 @@ def extra_workloads(dev, stream):
         "schedule_ms": {k: round(v, 5) for k, v in tuned.items()},
         "fp32_ms": round(ums, 5), "fp32_GBps": round(16 * tot / (ums * 1e-3) / 1e9, 1),
         "hip_graph_replay_ms": round(gms, 5), "hip_graph_replay_bit_equal": graph_equal,
+        "hip_graph_10_execs_per_exec_ms": round(g10ms, 5),
         "fp16_storage_ms": round(ums16, 5),
         "fp16_storage_GBps": round(8 * tot / (ums16 * 1e-3) / 1e9, 1),
         "GFLOPs_5nlogn_fp32": round(up.info["flops_5nlogn"] / (ums * 1e-3) / 1e9, 1),
