@@ -521,6 +521,47 @@ def test_uneven_with_long_transforms():
     plan.close()
 
 
+@pytest.mark.parametrize("logn,B", [(12, 1500), (13, 700), (14, 300), (16, 70), (17, 6)])
+@pytest.mark.parametrize("c16", [False, True])
+def test_schedules_agree_adjoint_and_fp16(logn, B, c16):
+    """Every schedule of a uniform plan (table in global memory or LDS,
+    resident grids, two-pass grids, multi-pass splits and segment sizes)
+    gives bit-identical results for the adjoint too, and with FP16 storage
+    in both directions; the first schedule's results match the oracle."""
+    say(f"schedules agree: N=2^{logn} B={B} fp16={c16}")
+    x = workloads.uniform(9300 + logn, (B, 1 << logn)).astype(np.complex64)
+    if c16:
+        host = np.stack([x.real, x.imag], -1).astype(np.float16)
+        xin = host[..., 0].astype(np.float64) + 1j * host[..., 1].astype(np.float64)
+        t = torch.from_numpy(host).to(DEV).view(torch.complex32).reshape(B, -1)
+        p = qft.Plan(logn, B, qft.QFT_C16)
+    else:
+        xin = x.astype(np.complex128)
+        t = torch.from_numpy(x).to(DEV)
+        p = qft.Plan(logn, B)
+    names = p.schedules
+    assert len(names) > 1
+    outs = []
+    for i in range(len(names)):
+        p.schedule = i
+        outs.append((p.forward(t), p.adjoint(t)))
+    torch.cuda.synchronize()
+    for i, (f, b) in enumerate(outs[1:], 1):
+        assert torch.equal(f, outs[0][0]), names[i]
+        assert torch.equal(b, outs[0][1]), names[i]
+
+    def host_of(y):
+        if not c16:
+            return y.cpu().numpy().astype(np.complex128)
+        o = y.view(torch.float16).reshape(B, -1, 2).float().cpu().numpy().astype(np.float64)
+        return o[..., 0] + 1j * o[..., 1]
+
+    check(host_of(outs[0][0]), ref_fwd(xin), logn, fp16=c16, what=f"2^{logn} schedules fwd")
+    check(host_of(outs[0][1]), np.conj(ref_fwd(np.conj(xin))), logn, fp16=c16,
+          what=f"2^{logn} schedules adjoint")
+    p.close()
+
+
 def test_uneven_runs_of_long_transforms():
     """Runs of same-size long transforms that lie back to back (2^15, 2^16,
     2^17; the 2^16 run longer than one batched launch holds, 2^22 cells)
