@@ -188,7 +188,10 @@ qft_status qft_plan_info(qft_plan_t plan, int64_t* total_points, int64_t* algo_b
  *    {12,12,12,14,14}, {12,12,12,13,14}, {10,11,12,13,14}, {10,11,12,14,14},
  *    {10,12,12,13,14} (duplicates for the sizes present removed), sizes with
  *    one tile size sharing one launch, each as a resident persistent grid and
- *    as one workgroup per tile ("/all"); names read "t<T>:<r range>+..".
+ *    as one workgroup per tile ("/all"), and ("/pipe") with every group that
+ *    holds only transforms of 2^13 or 2^14 points, more tiles than resident
+ *    workgroups, on a resident grid that loads each next tile while the
+ *    current one runs; names read "t<T>:<r range>+..".
  *    Schedule 0 runs every transform of up to 2^14 points in ONE persistent
  *    launch.  Longer transforms run after them with the default two-pass or
  *    multi-pass schedule, a run of same-size ones that lie back to back as

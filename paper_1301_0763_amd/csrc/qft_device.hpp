@@ -1867,37 +1867,82 @@ QFT_HD void tile_body_s(const IO& io, WP W, int Tact, const float* sec, int tid,
   tile_rest_s<LOGN, T, NT, WAVE>(io, W, Tact, sec, tid, sync, wsync);
 }
 
-// Persistent tiles of a contiguous batch: the workgroup takes tiles first,
-// first + stride, .. < ntiles (tile w: transforms [w T, w T + T) of the
-// batch, the last one ragged) and loads each next tile's x into registers
-// while the current one runs its rounds in LDS, so that the loads overlap
-// the LDS work.  The rounds must not read global memory (sec in LDS): the
-// vector memory counter is in order, and a read issued after the loads
-// would wait for them.
-// Before its first fold it calls pre() (the kernel's copy of the constant
-// table into LDS, issued behind the first tile's loads).
-template <int LOGN, int T, int NT, int WAVE, int DT, bool SWAP, class Sync, class WSync,
-          typename WP, class Pre>
-QFT_HD void tile_loop_s(const typename Store<DT>::T* x, typename Store<DT>::T* X,
-                        int64_t batch, int64_t first, int64_t stride, WP W, const float* sec,
-                        int tid, Sync sync, WSync wsync, Pre pre) {
+// Tile sources of tile_loop_s: how many tiles, a tile's descriptor, and from
+// that the accessor and the transform count of the tile.
+//  * a contiguous batch of `batch` transforms of 2^LOGN points, T per tile
+//    (the last tile ragged); the descriptor is the tile index;
+template <int DT, bool SWAP, int LOGN, int T>
+struct ContigTiles {
   using IO = ContigIO<DT, SWAP, LOGN>;
-  const int64_t ntiles = (batch + T - 1) / T;
+  using Desc = int64_t;
+  const typename Store<DT>::T* x;
+  typename Store<DT>::T* X;
+  int64_t batch;
+  QFT_HD int64_t ntiles() const { return (batch + T - 1) / T; }
+  QFT_HD Desc desc(int64_t w) const { return w; }
+  QFT_HD IO io(Desc w) const { return IO(x + ((w * T) << LOGN), X + ((w * T) << LOGN)); }
+  QFT_HD int count(Desc w) const { return (int)(batch - w * T < T ? batch - w * T : T); }
+};
+//  * the tile list of an uneven plan's group whose tiles each hold one
+//    transform of 2^LOGN points: tile w = (log2n, first, 1, 0), the
+//    transform at element offset offs[first].  Both lists are read-only for
+//    the launch, so on the GPU they are read through the constant address
+//    space: scalar loads, which do not wait behind the vector loads of the
+//    next tile in flight (the offset is resolved once per tile, so the
+//    combine's stores need no load either).
+template <typename P>
+QFT_HD P read_only(const P* p, int64_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ((const __attribute__((address_space(4))) P*)p)[i];
+#else
+  return p[i];
+#endif
+}
+template <int DT, bool SWAP, int LOGN>
+struct ListTiles {
+  using IO = ContigIO<DT, SWAP, LOGN>;
+  using Desc = int64_t;  // element offset of the tile's transform
+  const typename Store<DT>::T* x;
+  typename Store<DT>::T* X;
+  const int4* tiles;
+  const int64_t* offs;
+  int64_t n;
+  QFT_HD int64_t ntiles() const { return n; }
+  QFT_HD Desc desc(int64_t w) const { return read_only(offs, (int64_t)read_only(tiles, w).y); }
+  QFT_HD IO io(Desc o) const { return IO(x + o, X + o); }
+  QFT_HD int count(Desc) const { return 1; }
+};
+
+// Persistent tiles: the workgroup takes tiles first, first + stride, .. <
+// src.ntiles() and loads each next tile's x into registers while the
+// current one runs its rounds in LDS, so that the loads overlap the LDS
+// work.  The rounds must not read global memory (sec in LDS): the vector
+// memory counter is in order, and a read issued after the loads would wait
+// for them.  Before its first fold it calls pre() (the kernel's copy of the
+// constant table into LDS, issued behind the first tile's loads).
+template <int LOGN, int T, int NT, int WAVE, class Src, class Sync, class WSync, typename WP,
+          class Pre>
+QFT_HD void tile_loop_s(const Src& src, int64_t first, int64_t stride, WP W, const float* sec,
+                        int tid, Sync sync, WSync wsync, Pre pre) {
+  using IO = typename Src::IO;
+  const int64_t ntiles = src.ntiles();
   if (first >= ntiles) return;
-  auto io_of = [&](int64_t w) { return IO(x + ((w * T) << LOGN), X + ((w * T) << LOGN)); };
-  auto count_of = [&](int64_t w) { return (int)(batch - w * T < T ? batch - w * T : T); };
   typename IO::Raw raw[tile_items<LOGN, T, NT>()];
-  tile_fetch_s<LOGN, T, NT>(io_of(first), count_of(first), tid, raw);
+  typename Src::Desc d = src.desc(first);
+  tile_fetch_s<LOGN, T, NT>(src.io(d), src.count(d), tid, raw);
   pre();
   for (int64_t w = first;;) {
     // per tile, so that the compiler does not hold every thread-dependent
     // LDS address of the bodies live across the loop
     launder(tid);
-    const IO io = io_of(w);
-    const int cnt = count_of(w);
+    const IO io = src.io(d);
+    const int cnt = src.count(d);
     tile_fold_s<LOGN, T, NT>(io, W, cnt, tid, raw);
     const int64_t wn = w + stride;
-    if (wn < ntiles) tile_fetch_s<LOGN, T, NT>(io_of(wn), count_of(wn), tid, raw);
+    if (wn < ntiles) {
+      d = src.desc(wn);
+      tile_fetch_s<LOGN, T, NT>(src.io(d), src.count(d), tid, raw);
+    }
     tile_rest_s<LOGN, T, NT, WAVE>(io, W, cnt, sec, tid, sync, wsync);
     if (wn >= ntiles) break;
     sync();  // the combine's LDS reads before the next fold's stores

@@ -73,6 +73,11 @@ struct TileGroup {
   int64_t ubatch;
   int64_t rows;  // real-input plans: real signals (2 per transform slot)
   bool lds_sec = false;
+  // uneven groups: the one size of all its tiles (0 if several), and whether
+  // such a group of 2^13- or 2^14-point transforms runs on a resident grid
+  // that loads each next tile during the current one
+  int single_log2n = 0;
+  bool pipe = false;
 };
 
 // Pointers of a real-input exec: rdft in0 -> out0; DCT-0/DST-0 in0 (c) ->

@@ -286,6 +286,7 @@ qft_status uneven_group(qft_plan_s* p, const int32_t* log2n, const std::vector<i
   qftk::build_tiles(log2n, offsets, lo, hi, tl, desc, perm);
   *g = qftk::TileGroup{tl, (int)desc.size(), group_grid(p, tl, (int64_t)desc.size(), true),
                        nullptr, nullptr, 0, 0, 0};
+  g->single_log2n = lo == hi ? lo : 0;
   if (desc.empty()) return QFT_SUCCESS;
   std::vector<int4> tiles;
   for (const qftk::TileDesc& d : desc) tiles.push_back(make_int4(d.log2n, d.first, d.count, 0));
@@ -816,6 +817,22 @@ qft_status qft_plan_create_uneven(qft_plan_t* plan, const int32_t* log2n, int64_
     all.name += "/all";
     for (qftk::TileGroup& g : all.groups) g.grid = std::max(g.ntiles, 1);
     p->schedules.push_back(all);
+  }
+  // "/pipe": the groups that hold only transforms of 2^13 or 2^14 points (one
+  // per tile) run on a resident grid that loads each next tile during the
+  // current one, where they have more tiles than resident workgroups
+  for (const Schedule& sc : persistent) {
+    Schedule pp = sc;
+    bool any = false;
+    for (qftk::TileGroup& g : pp.groups) {
+      if (g.single_log2n == g.tl && g.tl >= 13 && g.ntiles > g.grid) {
+        g.pipe = true;
+        any = true;
+      }
+    }
+    if (!any) continue;
+    pp.name += "/pipe";
+    p->schedules.push_back(pp);
   }
   if (s == QFT_SUCCESS) s = alloc_common(p);
   if (s != QFT_SUCCESS) {

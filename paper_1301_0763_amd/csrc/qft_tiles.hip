@@ -13,7 +13,9 @@
 //    current one runs;
 //  * tile_kernel_g: the persistent kernel of uneven plans; a workgroup takes
 //    tiles w = blockIdx.x, blockIdx.x + gridDim.x, ... of a size-sorted list
-//    and runs the compile-time specialised body of each tile's size.
+//    and runs the compile-time specialised body of each tile's size;
+//  * tile_kernel_pg: an uneven group of 2^13- or 2^14-point transforms only,
+//    on a resident grid that loads each next tile during the current one.
 // Both run qftk::tile_body_s (fold, forward and backward rounds, fused
 // DCT-0/DST-0 chain with the combine), reading and writing HBM once.
 #include "qft_kernels.hpp"
@@ -88,10 +90,28 @@ __global__ __launch_bounds__(tile_threads_one(LOGN, TL)) void tile_kernel_p(cons
   __shared__ float Sl[lds_secants<LOGN>()];
   const PadPtr<kPad> W{Wl, 0};
   const int tid = (int)threadIdx.x;
-  tile_loop_s<LOGN, T, NT, kWave, DT, SWAP>(x, X, batch, (int64_t)blockIdx.x,
-                                            (int64_t)gridDim.x, W, Sl, tid, DevSync{},
-                                            DevWaveSync{},
-                                            [&]() { secants_to_lds<LOGN, NT>(Sl, sec, tid); });
+  tile_loop_s<LOGN, T, NT, kWave>(ContigTiles<DT, SWAP, LOGN, T>{x, X, batch},
+                                  (int64_t)blockIdx.x, (int64_t)gridDim.x, W, Sl, tid,
+                                  DevSync{}, DevWaveSync{},
+                                  [&]() { secants_to_lds<LOGN, NT>(Sl, sec, tid); });
+}
+
+// An uneven group whose tiles each hold one transform of 2^TL points (TL =
+// 13, 14), on a resident grid that loads each next tile during the current
+// one (tile_loop_s over the group's tile list), 32 cells per thread.
+template <int TL, int DT, bool SWAP>
+__global__ __launch_bounds__(tile_threads_one(TL, TL)) void tile_kernel_pg(
+    const typename Store<DT>::T* x, typename Store<DT>::T* X, const int4* __restrict__ tiles,
+    const int64_t* __restrict__ offs, int ntiles, const float* sec) {
+  constexpr int NT = tile_threads_one(TL, TL);
+  __shared__ float2 Wl[padded_cells<kPad>(1 << TL)];
+  __shared__ float Sl[lds_secants<TL>()];
+  const PadPtr<kPad> W{Wl, 0};
+  const int tid = (int)threadIdx.x;
+  tile_loop_s<TL, 1, NT, kWave>(
+      ListTiles<DT, SWAP, TL>{x, X, tiles, offs, ntiles},
+      (int64_t)blockIdx.x, (int64_t)gridDim.x, W, Sl, tid, DevSync{}, DevWaveSync{},
+      [&]() { secants_to_lds<TL, NT>(Sl, sec, tid); });
 }
 
 template <int TL, int DT, bool SWAP, int LOGN>
@@ -229,6 +249,17 @@ hipError_t launch_tiles(const TileGroup& g, const void* in, void* out, const flo
   if (g.tl != TL || g.ntiles <= 0) return hipErrorInvalidValue;
   if (!g.d_tiles) return launch_uniform<DT, TL, SWAP, 1>(g, in, out, sec, st);
   if (g.grid <= 0 || g.grid > g.ntiles) return hipErrorInvalidValue;
+  if (g.pipe) {
+    if constexpr (TL >= 13) {
+      if (g.single_log2n != TL) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((tile_kernel_pg<TL, DT, SWAP>), dim3((unsigned)g.grid),
+                         dim3(tile_threads_one(TL, TL)), 0, st, (const E*)in, (E*)out,
+                         g.d_tiles, g.d_offs, g.ntiles, sec);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   hipLaunchKernelGGL((tile_kernel_g<TL, DT, SWAP>), dim3((unsigned)g.grid),
                      dim3(tile_threads(TL)), 0, st, (const E*)in, (E*)out, g.d_tiles, g.d_offs,
                      g.ntiles, sec);

@@ -37,6 +37,7 @@ def load():
     L.emu_twopass.argtypes = [i, i, vp, vp, i, i64, i64]
     L.emu_tile_s.argtypes = [i, i, vp, vp, i, i, vp]
     L.emu_tile_p.argtypes = [i, i, vp, vp, i, i64, i64]
+    L.emu_tile_pg.argtypes = [i, i, vp, vp, i, vp, vp, i64, i64]
     L.emu_tile_real.argtypes = [i, i, i, i64, vp, vp, vp, vp]
     L.emu_multipass_real.argtypes = [i, i, i, i64, vp, vp, vp, vp, i, i]
     L.emu_race_model_check.argtypes = [i, i]
@@ -48,6 +49,7 @@ def load():
     L.emu_fixed.argtypes = [vp, vp, i, i64, i]
     L.emu_fixed_table.argtypes = [i, vp, vp]
     for f in (L.emu_multipass, L.emu_uneven, L.emu_twopass, L.emu_tile_s, L.emu_tile_p,
+              L.emu_tile_pg,
               L.emu_tile_real, L.emu_multipass_real, L.emu_race_model_check,
               L.emu_multipass_levels, L.emu_cache_store, L.emu_cache_lookup, L.emu_cache_path,
               L.emu_fixed, L.emu_fixed_table):

@@ -285,8 +285,34 @@ int tile_p_impl(const void* x, void* X, int64_t batch, int64_t grid, const float
     Tracker tr(NT);
     TPtr W{lds.data(), 0, &tr, cells, kEmuPad};
     run_workgroup(NT, tr, [&](int tid, auto sync, auto wsync) {
-      qftk::tile_loop_s<LOGN, T, NT, 64, DT, SWAP>((const E*)x, (E*)X, batch, b, grid, W, sec,
-                                                  tid, sync, wsync, []() {});
+      qftk::tile_loop_s<LOGN, T, NT, 64>(qftk::ContigTiles<DT, SWAP, LOGN, T>{(const E*)x, (E*)X,
+                                                                            batch},
+                                        b, grid, W, sec, tid, sync, wsync, []() {});
+    });
+    if (tr.oob) return -100;
+    races += tr.races;
+  }
+  return (int)races;
+}
+
+// The resident-grid kernel of an uneven group of one-transform tiles
+// (tile_kernel_pg): tile w = tiles[w] = (log2n, first, 1, 0), the transform
+// at element offset offs[first]; the GPU's threads for a 2^LOGN tile.
+template <int DT, bool SWAP, int LOGN>
+int tile_pg_impl(const void* x, void* X, const int4* tiles, const int64_t* offs, int64_t ntiles,
+                 int64_t grid, const float* sec) {
+  using E = typename qftk::Store<DT>::T;
+  constexpr int NT = emu_tile_threads<LOGN, LOGN>(false);
+  const int64_t cells = (int64_t)1 << LOGN;
+  int64_t races = 0;
+  for (int64_t b = 0; b < grid; ++b) {
+    std::vector<float2> lds(cells + (cells >> kEmuPad));
+    Tracker tr(NT);
+    TPtr W{lds.data(), 0, &tr, cells, kEmuPad};
+    run_workgroup(NT, tr, [&](int tid, auto sync, auto wsync) {
+      qftk::tile_loop_s<LOGN, 1, NT, 64>(
+          qftk::ListTiles<DT, SWAP, LOGN>{(const E*)x, (E*)X, tiles, offs, ntiles}, b, grid, W,
+          sec, tid, sync, wsync, []() {});
     });
     if (tr.oob) return -100;
     races += tr.races;
@@ -721,6 +747,21 @@ int emu_tile_s(int dt, int swap, const void* x, void* X, int logn, int Tact,
                            : tile_s_dispatch<0, false>(x, X, logn, Tact, sec.data(), offs);
   return swap ? tile_s_dispatch<1, true>(x, X, logn, Tact, sec.data(), offs)
               : tile_s_dispatch<1, false>(x, X, logn, Tact, sec.data(), offs);
+}
+
+// The resident-grid kernel of an uneven group of 2^13- or 2^14-point
+// transforms, one per tile (tiles: int4 per tile, (log2n, first, 1, 0)).
+int emu_tile_pg(int dt, int swap, const void* x, void* X, int logn, const int32_t* tiles,
+                const int64_t* offs, int64_t ntiles, int64_t grid) {
+  if (ntiles < 1 || grid < 1 || (logn != 13 && logn != 14)) return -1;
+  std::vector<float> sec = secants(logn);
+  const int4* t = reinterpret_cast<const int4*>(tiles);
+  if (dt != 0) return -1;
+  if (logn == 13)
+    return swap ? tile_pg_impl<0, true, 13>(x, X, t, offs, ntiles, grid, sec.data())
+                : tile_pg_impl<0, false, 13>(x, X, t, offs, ntiles, grid, sec.data());
+  return swap ? tile_pg_impl<0, true, 14>(x, X, t, offs, ntiles, grid, sec.data())
+              : tile_pg_impl<0, false, 14>(x, X, t, offs, ntiles, grid, sec.data());
 }
 
 // The resident-grid tile kernel (tile_kernel_p) with `grid` workgroups.

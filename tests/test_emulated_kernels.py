@@ -234,6 +234,39 @@ def test_resident_grid_tiles(emu, logn, batch, grid, swap):
     assert np.array_equal(out2, ref)
 
 
+@pytest.mark.parametrize("logn", [13, 14])
+@pytest.mark.parametrize("swap", [0, 1])
+def test_resident_grid_uneven_list(emu, logn, swap):
+    """The resident-grid kernel of an uneven group of one-transform tiles:
+    it walks the group's tile list (tiles in a different order than the
+    transforms lie in memory, between transforms of other sizes), resolves
+    each transform's offset once per tile and loads the next tile during the
+    current one; bit-identical to the tile kernel on each transform."""
+    N = 1 << logn
+    rng = np.random.default_rng(31 + logn)
+    count = 5
+    gaps = rng.integers(1, 300, count)  # other transforms' points between them
+    offs = np.cumsum(gaps + np.r_[0, np.full(count - 1, N)]).astype(np.int64)
+    total = int(offs[-1] + N + 17)
+    x = _as_c64(workloads.uniform(950 + logn, (1, total)))[0]
+    order = rng.permutation(count)
+    tiles = np.zeros((count, 4), np.int32)
+    tiles[:, 0] = logn
+    tiles[:, 1] = order
+    tiles[:, 2] = 1
+    out = np.zeros_like(x)
+    assert emu.emu_tile_pg(0, swap, x.ctypes.data, out.ctypes.data, logn, tiles.ctypes.data,
+                           offs.ctypes.data, count, 2) == 0
+    untouched = np.ones(total, bool)
+    for o in offs:
+        seg = np.ascontiguousarray(x[o:o + N][None])
+        ref = np.zeros_like(seg)
+        assert emu.emu_tile_s(0, swap, seg.ctypes.data, ref.ctypes.data, logn, 1, None) == 0
+        assert np.array_equal(out[o:o + N], ref[0])
+        untouched[o:o + N] = False
+    assert not out[untouched].any()
+
+
 @pytest.mark.parametrize("logn", range(1, 15))
 def test_specialised_tile_as_launched(emu, logn):
     """The compile-time specialised tile kernel with the GPU's own tile size

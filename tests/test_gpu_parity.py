@@ -333,7 +333,9 @@ def test_uniform_and_uneven_kernels_agree(logn, B):
 
 def test_uneven_schedules_and_autotune():
     """The uneven plan's schedules (one persistent launch for every size, or
-    one launch per tile size) agree bit for bit, the adjoint too; autotune
+    one launch per tile size; persistent, one workgroup per tile, or with
+    the 2^14-point group on the resident grid that loads each next tile
+    during the current one) agree bit for bit, the adjoint too; autotune
     times them all and keeps one."""
     say("schedules: uneven c4 sizes")
     r, vals = workloads.make("c4")
@@ -341,9 +343,13 @@ def test_uneven_schedules_and_autotune():
     plan = qft.UnevenPlan(r.tolist())
     names = plan.schedules
     say(f"uneven schedules {names}")
-    # 7 tile-size assignments (2^10 .. 2^14 tiles), each persistent and "/all"
-    assert names[0] == "t14:6-14" and len(names) == 14
+    # 7 tile-size assignments (2^10 .. 2^14 tiles), each persistent and "/all",
+    # and "/pipe" for the four whose 2^14 tiles form a group of their own
+    # (455 tiles, more than the 256 resident workgroups)
+    assert names[0] == "t14:6-14" and len(names) == 18
     assert "t10:6-10+t11:11+t12:12+t13:13+t14:14" in names
+    pipes = [n for n in names if n.endswith("/pipe")]
+    assert len(pipes) == 4 and "t13:6-13+t14:14/pipe" in pipes
     fw, bw = [], []
     for i in range(len(names)):
         plan.schedule = i
