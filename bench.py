@@ -214,9 +214,9 @@ def extra_workloads(dev, stream):
     }
     p3.close()
     del x3t, y3
-    # fixed point (QFT_I32): complex int32 pairs, one workgroup per transform
+    # fixed point (QFT_I32): complex int32 pairs
     fx = {}
-    for lg, nb in ((12, 4096), (16, 64)):
+    for lg, nb in ((8, 16384), (12, 4096), (16, 64)):
         rng = np.random.default_rng(6 + lg)
         xi = torch.from_numpy(rng.integers(-(1 << (28 - lg)), 1 << (28 - lg), (nb, 1 << lg, 2))
                               .astype(np.int32)).to(dev)

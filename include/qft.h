@@ -96,7 +96,8 @@ qft_status qft_plan_create(qft_plan_t* plan, int log2n, int64_t batch, qft_dtype
  * for N <= 2^11, growing about 17% per doubling), it approximates X within
  * the rounding of about N log2 N - 3N products.  The plan allocates the
  * integer table and, for log2n > 12, 2*batch*N int32 pairs of scratch; exec
- * runs one workgroup per transform (in LDS up to 2^12 points).
+ * runs the transforms in LDS up to 2^12 points (2^12 / N of them per
+ * workgroup), beyond that one workgroup per transform.
  * qft_exec_bwd gives the adjoint by the same swap identity as below.
  */
 

@@ -669,11 +669,15 @@ def _fixed_ref(x):
 
 @pytest.mark.parametrize("logn,B", [(1, 3), (2, 3), (3, 3), (4, 5), (5, 4), (6, 3), (7, 3),
                                     (8, 3), (9, 3), (10, 3), (11, 2), (12, 3), (13, 2),
-                                    (14, 2), (15, 2), (16, 2)])
+                                    (14, 2), (15, 2), (16, 2),
+                                    (2, 2100), (4, 600), (8, 37), (11, 5)])
 def test_fixed_point_bit_exact(logn, B):
     """Fixed point (QFT_I32): forward and adjoint bit-identical to the integer
     oracle, on inputs within the overflow-free range and on full-range int32
-    inputs (wrapping); in range, close to the exact DFT."""
+    inputs (wrapping); in range, close to the exact DFT.  Small transforms
+    share a workgroup (2^12 / N of them, each with its own threads): the
+    batches with several workgroups and a partly filled last one check
+    that."""
     N = 1 << logn
     say(f"fixed point: N=2^{logn} B={B}")
     rng = np.random.default_rng(3300 + logn)
