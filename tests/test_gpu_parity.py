@@ -269,24 +269,38 @@ def test_plan_info():
     p.close()
 
 
-@pytest.mark.parametrize("kind", ["uneven", "two_pass", "tile"])
+@pytest.mark.parametrize("kind", ["uneven", "two_pass", "tile", "uneven_pipe", "tile_pipe",
+                                  "tile_lds", "multi_pass_s13"])
 def test_graph_capture_replays(kind):
     """exec neither allocates nor issues memsets, so it can be captured in a
     HIP graph (torch.cuda.CUDAGraph).  The graph is replayed several times with
     the program's own eager work and synchronisations in between, and every
     replay must equal the eager result bit for bit."""
     say(f"graph capture: {kind}")
-    if kind == "uneven":
+    if kind.startswith("uneven"):
         r, vals = workloads.make("c4")
         x = torch.from_numpy(vals).to(DEV)
         plan = qft.UnevenPlan(r.tolist())
     elif kind == "two_pass":
         x = torch.from_numpy(workloads.normal(77, (8, 1 << 16))).to(DEV)
         plan = qft.Plan(16, 8)
-
+    elif kind == "tile_pipe":
+        x = torch.from_numpy(workloads.uniform(79, (600, 1 << 14))).to(DEV)
+        plan = qft.Plan(14, 600)
+    elif kind == "tile_lds":
+        x = torch.from_numpy(workloads.uniform(80, (300, 1 << 12))).to(DEV)
+        plan = qft.Plan(12, 300)
+    elif kind == "multi_pass_s13":
+        x = torch.from_numpy(workloads.normal(81, (2, 1 << 17))).to(DEV)
+        plan = qft.Plan(17, 2)
     else:
         x = torch.from_numpy(workloads.uniform(78, (64, 1 << 10))).to(DEV)
         plan = qft.Plan(10, 64)
+    # the schedule under test (the resident-grid, LDS-table or 2^13-segment one)
+    suffix = {"uneven_pipe": "/pipe", "tile_pipe": "/pipe", "tile_lds": "/lds",
+              "multi_pass_s13": "/s13"}.get(kind)
+    if suffix:
+        plan.schedule = next(i for i, n in enumerate(plan.schedules) if n.endswith(suffix))
     eager = plan.forward(x)
     torch.cuda.synchronize()
     out = torch.empty_like(x)
