@@ -608,6 +608,9 @@ int multipass_real_impl(int kind, int logn, int64_t rows, const void* in0, const
 // the specialised tile kernel with the offset list; longer ones through the
 // multi-pass schedule (segments of 2^seg_log2 cells).
 template <int DT, bool SWAP>
+int twopass_impl(const void* x, void* X, int mc_log2, int64_t batch, int64_t grid);
+
+template <int DT, bool SWAP>
 int uneven_impl(const void* x, void* X, const int32_t* log2n, int64_t count, int seg_log2,
                 int nthr) {
   using E = typename qftk::Store<DT>::T;
@@ -624,10 +627,14 @@ int uneven_impl(const void* x, void* X, const int32_t* log2n, int64_t count, int
     if (r < 0) return r;
     races += r;
   }
+  // as the library runs them: 2^11 .. 2^14 one tile each, 2^15 and 2^16 the
+  // two-pass path (2^12- and 2^13-cell segments), longer ones multi-pass
   for (int64_t i : large) {
     const int r =
         log2n[i] <= 14
             ? tile_s_dispatch<DT, SWAP>(x, X, log2n[i], 1, sec.data(), off.data() + i)
+        : log2n[i] <= 16
+            ? twopass_impl<DT, SWAP>((const E*)x + off[i], (E*)X + off[i], log2n[i] - 3, 1, 0)
             : multipass_impl<DT, SWAP>((const E*)x + off[i], (E*)X + off[i], log2n[i], 1,
                                        seg_log2, nthr, sec.data());
     if (r < 0) return r;

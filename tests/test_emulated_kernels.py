@@ -113,9 +113,10 @@ def test_uneven_worklist(emu):
     """Packed uneven batch as the library runs it: sizes up to 2^10 share
     2^10-cell tiles of the size-sorted work list, 2^11 .. 2^14 take a tile of
     their own, all through the specialised tile kernel and the offset list;
-    2^15 goes multi-pass (segments of 2^3)."""
+    2^15 goes through the two-pass path (2^12-cell segments, the library's
+    threads), 2^17 multi-pass (segments of 2^3 here)."""
     rng = np.random.default_rng(3)
-    log2n = np.array(list(rng.integers(1, 13, 40)) + [13, 14, 15], dtype=np.int32)
+    log2n = np.array(list(rng.integers(1, 13, 40)) + [13, 14, 15, 17], dtype=np.int32)
     rng.shuffle(log2n)
     total = int(np.sum(1 << log2n.astype(np.int64)))
     vals = workloads.uniform(21, (total,))
