@@ -183,6 +183,29 @@ def test_c4_uneven_fp16_storage():
     assert _uneven("c16") <= 1.0
 
 
+def test_uneven_fp16_schedules_agree():
+    """FP16 storage on the uneven plan: every schedule (persistent, one
+    workgroup per tile, resident grid with the next tile's loads in flight)
+    gives bit-identical forward and adjoint results."""
+    say("c4 sizes, FP16 storage: every schedule")
+    r, vals = workloads.make("c4")
+    host = np.stack([vals.real, vals.imag], -1).astype(np.float16)
+    t = torch.from_numpy(host).to(DEV).view(torch.complex32).reshape(-1)
+    plan = qft.UnevenPlan(r.tolist(), qft.QFT_C16)
+    names = plan.schedules
+    assert any(n.endswith("/pipe") for n in names)
+    fw, bw = [], []
+    for i in range(len(names)):
+        plan.schedule = i
+        fw.append(plan.forward(t))
+        bw.append(plan.adjoint(t))
+    torch.cuda.synchronize()
+    for i in range(1, len(names)):
+        assert torch.equal(fw[i].view(torch.int16), fw[0].view(torch.int16)), names[i]
+        assert torch.equal(bw[i].view(torch.int16), bw[0].view(torch.int16)), names[i]
+    plan.close()
+
+
 def test_c5_autograd_loss_gradient():
     say("c5: N=4096 B=512 loss = sum w |X|^2, autograd")
     x, w = workloads.make("c5")
