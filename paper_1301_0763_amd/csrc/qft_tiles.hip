@@ -16,8 +16,9 @@
 //    and runs the compile-time specialised body of each tile's size;
 //  * tile_kernel_pg: an uneven group of 2^13- or 2^14-point transforms only,
 //    on a resident grid that loads each next tile during the current one.
-// Both run qftk::tile_body_s (fold, forward and backward rounds, fused
-// DCT-0/DST-0 chain with the combine), reading and writing HBM once.
+// All run the tile body of qft_device.hpp (tile_fetch_s, tile_fold_s,
+// tile_rest_s: fold, forward and backward rounds, fused DCT-0/DST-0 chain
+// with the combine), reading and writing HBM once.
 #include "qft_kernels.hpp"
 
 #if !defined(QFT_TILE_DT) || !defined(QFT_TILE_TL) || !defined(QFT_TILE_SWAP)
