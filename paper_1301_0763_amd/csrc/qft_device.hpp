@@ -728,7 +728,79 @@ QFT_HD void fwd_group_s(SP sd, int j, int x, const float* __restrict__ sec, bool
   }
 }
 
-template <int K, int HI, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0, typename WP>
+// b with its sign bit flipped where mask has it set (mask 0: b itself).
+QFT_HD float2 flip_sign(float2 b, unsigned mask) {
+  return make_float2(__builtin_bit_cast(float, __builtin_bit_cast(unsigned, b.x) ^ mask),
+                     __builtin_bit_cast(float, __builtin_bit_cast(unsigned, b.y) ^ mask));
+}
+
+// fwd_group_s for both sides in one code path: the DCT side keeps a + b and
+// scales a - b, the DST side keeps a - b and scales a + b, so both are a + b'
+// and (a - b') h with b' = b, or -b (exact) where dst_mask holds the sign bit.
+template <int K, int S, typename SP>
+QFT_HD void fwd_group_sf(SP sd, int j, int x, const float* __restrict__ sec, bool skip0,
+                         unsigned dst_mask) {
+  constexpr int G = S >> K;
+  constexpr int NE = 2 << K;
+  const int base = j * S;
+  float2 e[NE];
+  // rows at x and G-1-x when G is a multiple of kRowCells
+  constexpr bool ROWS = G % kRowCells == 0;
+  const auto rx = pad_row(sd, base + x);
+  const auto rm = pad_row(sd, base + G - 1 - x);
+#pragma unroll
+  for (int c = 0; c < (1 << K); ++c) {
+    if constexpr (ROWS) {
+      e[2 * c] = rx[c * G];
+      e[2 * c + 1] = rm[c * G];
+    } else {
+      e[2 * c] = sd[base + c * G + x];
+      e[2 * c + 1] = sd[base + c * G + G - 1 - x];
+    }
+  }
+#pragma unroll
+  for (int m = K; m >= 1; --m) {
+    const int span = 1 << m, half = span >> 1;
+    const int L = G << (m - 1);
+    float2 o[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) o[i] = e[i];
+#pragma unroll
+    for (int c0 = 0; c0 < (1 << K); c0 += span) {
+      if (c0 == 0 && skip0 && j == 0) continue;
+#pragma unroll
+      for (int cc = 0; cc < half; ++cc) {
+        const int c = c0 + cc, cm = c0 + span - 1 - cc;
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          const float2 a = e[2 * c + f], b = flip_sign(e[2 * cm + 1 - f], dst_mask);
+          const float hsec = f ? sec[L + cc * G + G - 1 - x] : sec[L + cc * G + x];
+          o[2 * c + f] = cadd(a, b);
+          o[2 * (c + half) + f] = cscale(csub(a, b), hsec);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NE; ++i) e[i] = o[i];
+  }
+#pragma unroll
+  for (int c = 0; c < (1 << K); ++c) {
+    if constexpr (ROWS) {
+      rx[c * G] = e[2 * c];
+      rm[c * G] = e[2 * c + 1];
+    } else {
+      sd[base + c * G + x] = e[2 * c];
+      sd[base + c * G + G - 1 - x] = e[2 * c + 1];
+    }
+  }
+}
+
+// SF: one branch-free code path for both sides (the side's sign mask at run
+// time), else a branch per item between the two sides' own code.  Which is
+// faster depends on the kernel (the branch-free one issues two more
+// instructions per butterfly and no moves where the branches join).
+template <int K, int HI, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0, bool SF,
+          typename WP>
 QFT_HD void fwd_chunk_s(WP W, const float* sec, int tid) {
   using Map = PassMap<NS, LGS, NT, WAVE, K + 1, HI>;
   constexpr int lgGroups = LGS - K - 1;
@@ -744,10 +816,13 @@ QFT_HD void fwd_chunk_s(WP W, const float* sec, int tid) {
     const int j = g >> lgHalfG;
     const int x = g & ((1 << lgHalfG) - 1);
     auto sd = W + (s << LGS);
-    if (MODE == SIDES_DST || (MODE == SIDES_ALT && (s & 1)))
-      fwd_group_s<K, (1 << HI), true>(sd, j, x, sec, SKIP0);
-    else
-      fwd_group_s<K, (1 << HI), false>(sd, j, x, sec, SKIP0);
+    const bool dst = MODE == SIDES_DST || (MODE == SIDES_ALT && (s & 1));
+    if constexpr (SF) {
+      fwd_group_sf<K, (1 << HI)>(sd, j, x, sec, SKIP0, dst ? 0x80000000u : 0u);
+    } else {
+      if (dst) fwd_group_s<K, (1 << HI), true>(sd, j, x, sec, SKIP0);
+      else fwd_group_s<K, (1 << HI), false>(sd, j, x, sec, SKIP0);
+    }
   }
 }
 
@@ -854,14 +929,14 @@ QFT_HD constexpr bool fwd_next_local() {
 // forward chunks for rounds (KT, HI], top down, each followed by the
 // ordering the next pass needs
 template <int HI, int KT, int KC, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0,
-          class Sync, class WSync, typename WP>
+          bool SF, class Sync, class WSync, typename WP>
 QFT_HD void fwd_rounds_s(WP W, const float* sec, int tid, Sync sync, WSync wsync) {
   if constexpr (HI > KT) {
     constexpr int K = cmin<KC, HI - KT>::v;
-    fwd_chunk_s<K, HI, LGS, NS, NT, WAVE, MODE, SKIP0>(W, sec, tid);
+    fwd_chunk_s<K, HI, LGS, NS, NT, WAVE, MODE, SKIP0, SF>(W, sec, tid);
     pass_sync<PassMap<NS, LGS, NT, WAVE, K + 1, HI>::local &&
               fwd_next_local<HI - K, KT, KC, LGS, NS, NT, WAVE>()>(sync, wsync);
-    fwd_rounds_s<HI - K, KT, KC, LGS, NS, NT, WAVE, MODE, SKIP0>(W, sec, tid, sync, wsync);
+    fwd_rounds_s<HI - K, KT, KC, LGS, NS, NT, WAVE, MODE, SKIP0, SF>(W, sec, tid, sync, wsync);
   }
 }
 
@@ -893,13 +968,13 @@ QFT_HD void bwd_rounds_s(WP W, int tid, Sync sync, WSync wsync) {
 // Forward rounds S = 2^TOP .. 2 and backward rounds back up (TOP >= 1).
 // Expects a workgroup barrier before and ends with one; in between, passes
 // whose segments fit one wave's cells are ordered by the wave alone.
-template <int TOP, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0, class Sync,
-          class WSync, typename WP>
+template <int TOP, int LGS, int NS, int NT, int WAVE, int MODE, bool SKIP0, bool SF = false,
+          class Sync, class WSync, typename WP>
 QFT_HD void sweeps_s(WP W, const float* sec, int tid, Sync sync, WSync wsync) {
   if constexpr (TOP >= 1) {
     constexpr int KC = sweep_kc<NS, LGS, NT>();
     constexpr int KT = sweep_tail_rounds(TOP, KC);
-    fwd_rounds_s<TOP, KT, KC, LGS, NS, NT, WAVE, MODE, SKIP0>(W, sec, tid, sync, wsync);
+    fwd_rounds_s<TOP, KT, KC, LGS, NS, NT, WAVE, MODE, SKIP0, SF>(W, sec, tid, sync, wsync);
     tail_chunk_s<KT, LGS, NS, NT, WAVE, MODE, SKIP0>(W, sec, tid);
     pass_sync<PassMap<NS, LGS, NT, WAVE, KT, KT>::local &&
               bwd_local<KT + 1, TOP, KC, LGS, NS, NT, WAVE>()>(sync, wsync);
@@ -1826,7 +1901,8 @@ QFT_HD void tile_fold_s(const IO& io, WP W, int Tact, int tid,
 
 // Starts with a workgroup barrier (the fold's LDS stores); ends with the
 // combine's LDS reads, unordered.
-template <int LOGN, int T, int NT, int WAVE, class Sync, class WSync, typename WP, class IO>
+template <int LOGN, int T, int NT, int WAVE, bool SF = false, class Sync, class WSync,
+          typename WP, class IO>
 QFT_HD void tile_rest_s(const IO& io, WP W, int Tact, const float* sec, int tid, Sync sync,
                         WSync wsync) {
   constexpr int n = 1 << LOGN, h = n >> 1;
@@ -1834,7 +1910,8 @@ QFT_HD void tile_rest_s(const IO& io, WP W, int Tact, const float* sec, int tid,
   const int tot_act = Tact << (LOGN - 1);
   sync();
   if constexpr (LOGN >= 3)
-    sweeps_s<LOGN - 2, LOGN - 1, 2 * T, NT, WAVE, SIDES_ALT, true>(W, sec, tid, sync, wsync);
+    sweeps_s<LOGN - 2, LOGN - 1, 2 * T, NT, WAVE, SIDES_ALT, true, SF>(W, sec, tid, sync,
+                                                                       wsync);
   if constexpr (LOGN >= 5) {
     chain_fused<LOGN, T, NT, WAVE, true>(TileSides<WP>{W, LOGN}, io, Tact, tid, sync, wsync);
     return;
@@ -1858,13 +1935,15 @@ QFT_HD void tile_rest_s(const IO& io, WP W, int Tact, const float* sec, int tid,
   }
 }
 
-template <int LOGN, int T, int NT, int WAVE, class Sync, class WSync, typename WP, class IO>
+// SF as in fwd_chunk_s.
+template <int LOGN, int T, int NT, int WAVE, bool SF = false, class Sync, class WSync,
+          typename WP, class IO>
 QFT_HD void tile_body_s(const IO& io, WP W, int Tact, const float* sec, int tid, Sync sync,
                         WSync wsync) {
   typename IO::Raw raw[tile_items<LOGN, T, NT>()];
   tile_fetch_s<LOGN, T, NT>(io, Tact, tid, raw);
   tile_fold_s<LOGN, T, NT>(io, W, Tact, tid, raw);
-  tile_rest_s<LOGN, T, NT, WAVE>(io, W, Tact, sec, tid, sync, wsync);
+  tile_rest_s<LOGN, T, NT, WAVE, SF>(io, W, Tact, sec, tid, sync, wsync);
 }
 
 // Tile sources of tile_loop_s: how many tiles, a tile's descriptor, and from

@@ -27,6 +27,12 @@
 
 namespace qftk {
 
+// The uniform tile kernel's forward rounds: one code path for both sides
+// (16 cells per thread), else a branch between the sides' own code.
+constexpr bool tile_sign_flip(int logn, int tl) {
+  return tile_threads_one(logn, tl) == (1 << tl) / 16;
+}
+
 // The constant table of transforms up to 2^LOGN points (its first 2^LOGN / 4
 // floats, Sec. 6.1) copied into LDS, where the rounds read their secants
 // (the LDS reads are cheaper than table reads through the vector memory
@@ -48,7 +54,10 @@ __device__ __forceinline__ void secants_to_lds(float* sl, const float* __restric
 }
 
 // LSEC: the rounds read the constant table from a copy in LDS, else from
-// global memory (which is faster depends on the size and the batch).
+// global memory (which is faster depends on the size and the batch).  With 16
+// cells per thread the forward rounds run one branch-free code path for both
+// sides (fwd_chunk_s), which measured faster there (2^12 x 4096: 63 against
+// 66 us, 2^10 x 32768: 139 against 143 us) and slower with 32.
 template <int LOGN, int TL, int DT, bool SWAP, bool LSEC>
 __global__ __launch_bounds__(tile_threads_one(LOGN, TL)) void tile_kernel_u(const typename Store<DT>::T* x,
                                                                    typename Store<DT>::T* X,
@@ -68,9 +77,11 @@ __global__ __launch_bounds__(tile_threads_one(LOGN, TL)) void tile_kernel_u(cons
     tile_fetch_s<LOGN, T, NT>(io, count, tid, raw);
     secants_to_lds<LOGN, NT>(Sl, sec, tid);
     tile_fold_s<LOGN, T, NT>(io, W, count, tid, raw);
-    tile_rest_s<LOGN, T, NT, kWave>(io, W, count, Sl, tid, DevSync{}, DevWaveSync{});
+    tile_rest_s<LOGN, T, NT, kWave, tile_sign_flip(LOGN, TL)>(io, W, count, Sl, tid, DevSync{},
+                                                              DevWaveSync{});
   } else {
-    tile_body_s<LOGN, T, NT, kWave>(io, W, count, sec, tid, DevSync{}, DevWaveSync{});
+    tile_body_s<LOGN, T, NT, kWave, tile_sign_flip(LOGN, TL)>(io, W, count, sec, tid, DevSync{},
+                                                              DevWaveSync{});
   }
 }
 

@@ -262,8 +262,11 @@ int tile_s_run(const void* x, void* X, int Tact, const float* sec, const int64_t
       const qftk::GatherIO<DT, SWAP> io((const E*)x, (E*)X, offs, LOGN);
       qftk::tile_body_s<LOGN, T, NT, 64>(io, W, Tact, sec, tid, sync, wsync);
     } else {
+      // the uniform kernel: one forward code path for both sides with 16
+      // cells per thread, as on the GPU
       const qftk::ContigIO<DT, SWAP, LOGN> io((const E*)x, (E*)X);
-      qftk::tile_body_s<LOGN, T, NT, 64>(io, W, Tact, sec, tid, sync, wsync);
+      qftk::tile_body_s<LOGN, T, NT, 64, NT == (1 << TL) / 16>(io, W, Tact, sec, tid, sync,
+                                                               wsync);
     }
   });
   return tr.oob ? -100 : (int)tr.races;
