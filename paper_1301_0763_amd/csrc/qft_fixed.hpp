@@ -58,11 +58,8 @@ struct Table {
   const int* shift;
 };
 
-QFT_HD int ilog2(int v) {
-  int r = 0;
-  while ((1 << (r + 1)) <= v) ++r;
-  return r;
-}
+// floor(log2 v), v >= 1
+QFT_HD int ilog2(int v) { return 31 - __builtin_clz((unsigned)v); }
 
 // Heap cell p >= 1 of a side holds the sample n = (2m + 1) N / (4M), M the
 // largest power of two <= p, m = p - M.
@@ -98,15 +95,16 @@ template <typename WP>
 QFT_HD void fwd_round(WP W, int logn, int S, Table tab, int tid, int nthr) {
   const int h = 1 << (logn - 1);
   const int L = S >> 1;
-  const int s = tab.shift[ilog2(L)];
+  const int lgS = ilog2(S);
+  const int s = tab.shift[lgS - 1];
   const int* H = tab.H + L;
-  const int segs = h / S - 1;               // j = 1 .. h/S - 1
-  const int quads = S >= 4 ? S >> 2 : 1;
-  const int items = 2 * segs * quads;
+  const int lgq = S >= 4 ? lgS - 2 : 0;     // quads per segment: 2^lgq
+  const int per_side = ((h >> lgS) - 1) << lgq;  // segments j = 1 .. h/S - 1
+  const int items = 2 * per_side;
   for (int i = tid; i < items; i += nthr) {
-    const int side = i / (segs * quads);
-    const int r = i - side * segs * quads;
-    const int j = 1 + r / quads, p = r - (r / quads) * quads;
+    const int side = i >= per_side ? 1 : 0;
+    const int r = i - side * per_side;
+    const int j = 1 + (r >> lgq), p = r & ((1 << lgq) - 1);
     auto y = W + side * h + j * S;
     const bool dst = side != 0;
     if (S == 2) {
@@ -137,6 +135,7 @@ template <typename RP, typename WP>
 QFT_HD void bwd_round(RP Win, WP Wout, int logn, int S, int tid, int nthr) {
   const int h = 1 << (logn - 1);
   const int L = S >> 1;
+  const int lgS = ilog2(S);
   for (int c = tid; c < 2 * h; c += nthr) {
     const int side = c >= h ? 1 : 0;
     const int q = c - side * h;
@@ -144,7 +143,7 @@ QFT_HD void bwd_round(RP Win, WP Wout, int logn, int S, int tid, int nthr) {
       Wout[c] = Win[c];
       continue;
     }
-    const int j = q / S, m = q - j * S, i = m >> 1;
+    const int j = q >> lgS, m = q & (S - 1), i = m >> 1;
     auto a = Win + side * h + j * S;
     auto t = a + L;
     int2 v;
