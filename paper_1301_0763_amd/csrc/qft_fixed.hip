@@ -53,9 +53,10 @@ inline FxShape fixed_shape(int log2n) {
 }
 
 // Workgroup b: transforms b T .. b T + T - 1, transform k of them taken by
-// threads k G .. k G + G - 1.  A group past the batch runs every pass with no
-// items (thread index N, beyond every pass's item count, which is at most N),
-// so that it meets the workgroup's barriers.
+// threads k G .. k G + G - 1 (G a power of two, so a group of at most 64
+// threads lies in one wavefront).  A group past the batch runs every pass with
+// no items (thread index N, beyond every pass's item count, which is at most
+// N), so that it meets the workgroup's barriers.
 template <bool SWAP, bool LDS>
 __global__ __launch_bounds__(1024) void fixed_kernel(const int2* x, int2* X, int logn,
                                                     int64_t batch, int T, const int* H,
@@ -67,8 +68,15 @@ __global__ __launch_bounds__(1024) void fixed_kernel(const int2* x, int2* X, int
   const int64_t N = (int64_t)1 << logn;
   int2* b0 = LDS ? lds + 2 * N * k : scratch + 2 * N * t;
   int2* b1 = b0 + N;
-  fx::transform(SwapIn<SWAP>{x + N * t}, SwapOut<SWAP>{X + N * t}, b0, b1, logn,
-                fx::Table{H, shift}, t < batch ? lt : (int)N, G, DevSync{});
+  const int tt = t < batch ? lt : (int)N;
+  // G <= 64 (N <= 2^8): each transform's threads and LDS buffers belong to
+  // one wavefront, so its passes are ordered by the wavefront alone
+  if (LDS && G <= kWave)
+    fx::transform(SwapIn<SWAP>{x + N * t}, SwapOut<SWAP>{X + N * t}, b0, b1, logn,
+                  fx::Table{H, shift}, tt, G, DevWaveSync{});
+  else
+    fx::transform(SwapIn<SWAP>{x + N * t}, SwapOut<SWAP>{X + N * t}, b0, b1, logn,
+                  fx::Table{H, shift}, tt, G, DevSync{});
 }
 
 }  // namespace

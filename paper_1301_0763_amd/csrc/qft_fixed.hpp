@@ -23,7 +23,7 @@
 //   combine          X(k), X(N-k) from the DCT cell k and the DST cell k
 // The buffers live in LDS (N <= 2^12) or in global scratch (2N cells per
 // transform).  This path is written for exactness and simplicity, not speed:
-// it takes one workgroup barrier per round and level.
+// it takes one barrier per round and level (a wavefront's for N <= 2^8).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -265,7 +265,8 @@ inline void fill_table_q(int* H, int* shift, int log2n_max) {
 }
 
 // One transform of 2^logn points, x -> X, with heap buffers B0, B1 of N
-// cells each; every pass ends with sync() (a workgroup barrier).
+// cells each; every pass ends with sync() (a workgroup barrier, or the
+// wavefront's own ordering where one wavefront holds the transform's threads).
 template <typename XP, typename OP, typename BP, class Sync>
 QFT_HD void transform(XP x, OP X, BP B0, BP B1, int logn, Table tab, int tid, int nthr,
                       Sync sync) {

@@ -865,8 +865,13 @@ int emu_fixed(const int32_t* x, int32_t* X, int logn, int64_t batch, int nthr) {
     IPtr B0{b0.data(), 0, &tr, N}, B1{b1.data(), 0, &tr, N};
     IPtr xi{(int2*)(const_cast<int32_t*>(x)) + b * N, 0, &tr, N};
     IPtr Xo{(int2*)X + b * N, 0, &tr, N};
-    run_workgroup(nthr, tr, [&](int tid, auto sync, auto) {
-      qftk::fx::transform(xi, Xo, B0, B1, logn, tab, tid, nthr, sync);
+    // at most one wavefront of threads: ordered by wavefront syncs alone, as
+    // on the GPU
+    run_workgroup(nthr, tr, [&](int tid, auto sync, auto wsync) {
+      if (nthr <= 64)
+        qftk::fx::transform(xi, Xo, B0, B1, logn, tab, tid, nthr, wsync);
+      else
+        qftk::fx::transform(xi, Xo, B0, B1, logn, tab, tid, nthr, sync);
     });
     if (tr.oob) return -100;
     races += tr.races;
