@@ -136,25 +136,32 @@ QFT_HD void bwd_round(RP Win, WP Wout, int logn, int S, int tid, int nthr) {
   const int h = 1 << (logn - 1);
   const int L = S >> 1;
   const int lgS = ilog2(S);
-  for (int c = tid; c < 2 * h; c += nthr) {
-    const int side = c >= h ? 1 : 0;
-    const int q = c - side * h;
+  const int hp = h >> 1;  // output pairs (cells 2i, 2i+1) per side
+  // item: one pair of output cells, so that every lane of a wavefront takes
+  // the same branch of its side (rounds exist for N >= 8, so h >= 4)
+  for (int c = tid; c < 2 * hp; c += nthr) {
+    const int side = c >= hp ? 1 : 0;
+    const int q = 2 * (c - side * hp);
+    auto in = Win + side * h;
+    auto out = Wout + side * h;
     if (q < S) {
-      Wout[c] = Win[c];
+      out[q] = in[q];
+      out[q + 1] = in[q + 1];
       continue;
     }
-    const int j = q >> lgS, m = q & (S - 1), i = m >> 1;
-    auto a = Win + side * h + j * S;
+    const int j = q >> lgS, i = (q & (S - 1)) >> 1;
+    auto a = in + j * S;
     auto t = a + L;
-    int2 v;
+    int2 ye, yo;
     if (side == 0) {
-      if ((m & 1) == 0) v = a[i];
-      else v = (i + 1 < L) ? add(t[i], t[i + 1]) : (int2)t[i];
+      ye = a[i];
+      yo = (i + 1 < L) ? add(t[i], t[i + 1]) : (int2)t[i];
     } else {
-      if ((m & 1) != 0) v = a[i];
-      else v = (i >= 1) ? add(t[i - 1], t[i]) : (int2)t[i];
+      yo = a[i];
+      ye = (i >= 1) ? add(t[i - 1], t[i]) : (int2)t[i];
     }
-    Wout[c] = v;
+    out[q] = ye;
+    out[q + 1] = yo;
   }
 }
 
