@@ -125,6 +125,72 @@ QFT_HD void fwd_round(WP W, int logn, int S, Table tab, int tid, int nthr) {
   }
 }
 
+// One forward quad in registers: the pairs (a, d) and (b, c) of a round's
+// closed quad {pa, pb, pc, pd} (values a, b, c, d), outputs in the same cells,
+// with the slice's constants H(pa), H(pb) and shift s (as in fwd_round).
+QFT_HD void fwd_quad(int2& a, int2& b, int2& c, int2& d, int ha, int hb, int s, bool dst) {
+  const int2 u1 = add(a, d), v1 = sub(a, d);
+  const int2 u2 = add(b, c), v2 = sub(b, c);
+  a = dst ? v1 : u1;
+  c = mul(dst ? u1 : v1, ha, s);
+  b = dst ? v2 : u2;
+  d = mul(dst ? u2 : v2, hb, s);
+}
+
+// Forward rounds S and S/2 (S >= 8) in one pass, the same operations as two
+// fwd_round passes.  With L = S/2 and M = S/4, round S's quads p and M-1-p
+// (p < S/8) of a segment j >= 1 hold the eight cells {p, M-1-p, M+p, L-1-p,
+// L+p, L+M-1-p, L+M+p, S-1-p}, which after that round are round S/2's quad p
+// of the segment's lower half and of its upper half: a closed group of eight.
+// Round S skips the head segment (j = 0), round S/2 only the lower half of it,
+// so the head's items are round S/2's quads of [L, S) alone.
+template <typename WP>
+QFT_HD void fwd_round2(WP W, int logn, int S, Table tab, int tid, int nthr) {
+  const int h = 1 << (logn - 1);
+  const int L = S >> 1, M = S >> 2;
+  const int lgS = ilog2(S);
+  const int s1 = tab.shift[lgS - 1], s2 = tab.shift[lgS - 2];
+  const int* H1 = tab.H + L;  // round S: slice L
+  const int* H2 = tab.H + M;  // round S/2: slice L/2
+  const int lgg = lgS - 3;    // groups per segment: S/8
+  const int per_side = (h >> lgS) << lgg;
+  for (int i = tid; i < 2 * per_side; i += nthr) {
+    const int side = i >= per_side ? 1 : 0;
+    const int r = i - side * per_side;
+    const int j = r >> lgg, p = r & ((1 << lgg) - 1);
+    auto y = W + side * h + j * S;
+    const bool dst = side != 0;
+    const int q = M - 1 - p;
+    if (j == 0) {
+      auto z = y + L;
+      int2 a = z[p], b = z[q], c = z[M + p], d = z[L - 1 - p];
+      fwd_quad(a, b, c, d, H2[p], H2[q], s2, dst);
+      z[p] = a;
+      z[q] = b;
+      z[M + p] = c;
+      z[L - 1 - p] = d;
+      continue;
+    }
+    int2 c0 = y[p], c1 = y[q], c2 = y[M + p], c3 = y[L - 1 - p];
+    int2 c4 = y[L + p], c5 = y[L + q], c6 = y[L + M + p], c7 = y[S - 1 - p];
+    // round S: quad p = {p, L-1-p, L+p, S-1-p}, quad q = {q, L-1-q, L+q, S-1-q}
+    // (L-1-q = M+p, S-1-q = L+M+p)
+    fwd_quad(c0, c3, c4, c7, H1[p], H1[L - 1 - p], s1, dst);
+    fwd_quad(c1, c2, c5, c6, H1[q], H1[M + p], s1, dst);
+    // round S/2: quad p of [0, L) = {p, q, M+p, L-1-p}, of [L, S) likewise
+    fwd_quad(c0, c1, c2, c3, H2[p], H2[q], s2, dst);
+    fwd_quad(c4, c5, c6, c7, H2[p], H2[q], s2, dst);
+    y[p] = c0;
+    y[q] = c1;
+    y[M + p] = c2;
+    y[L - 1 - p] = c3;
+    y[L + p] = c4;
+    y[L + q] = c5;
+    y[L + M + p] = c6;
+    y[S - 1 - p] = c7;
+  }
+}
+
 // Backward round S (eq. qft_4B interleave, eqs. qft_38B corrected / qft_38C,
 // the dst_oo special case) from Win into Wout: for every segment j >= 1 with
 // halves A = [jS, jS + S/2) and T = [jS + S/2, (j+1)S):
@@ -274,12 +340,19 @@ inline void fill_table_q(int* H, int* shift, int log2n_max) {
 // One transform of 2^logn points, x -> X, with heap buffers B0, B1 of N
 // cells each; every pass ends with sync() (a workgroup barrier, or the
 // wavefront's own ordering where one wavefront holds the transform's threads).
+// fuse2: forward rounds two per pass (fwd_round2) down to S = 8, which halves
+// those passes but also the items per pass.
 template <typename XP, typename OP, typename BP, class Sync>
 QFT_HD void transform(XP x, OP X, BP B0, BP B1, int logn, Table tab, int tid, int nthr,
-                      Sync sync) {
+                      Sync sync, bool fuse2) {
   fold(x, B0, logn, tid, nthr);
   sync();
-  for (int S = (1 << logn) >> 2; S >= 2; S >>= 1) {
+  int S = (1 << logn) >> 2;
+  for (; fuse2 && S >= 8; S >>= 2) {
+    fwd_round2(B0, logn, S, tab, tid, nthr);
+    sync();
+  }
+  for (; S >= 2; S >>= 1) {
     fwd_round(B0, logn, S, tab, tid, nthr);
     sync();
   }

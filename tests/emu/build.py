@@ -46,7 +46,7 @@ def load():
     L.emu_cache_store.argtypes = [cp, cp, cp]
     L.emu_cache_lookup.argtypes = [cp, cp, ctypes.c_char_p, i]
     L.emu_cache_path.argtypes = [ctypes.c_char_p, i]
-    L.emu_fixed.argtypes = [vp, vp, i, i64, i]
+    L.emu_fixed.argtypes = [vp, vp, i, i64, i, i]
     L.emu_fixed_table.argtypes = [i, vp, vp]
     for f in (L.emu_multipass, L.emu_uneven, L.emu_twopass, L.emu_tile_s, L.emu_tile_p,
               L.emu_tile_pg,

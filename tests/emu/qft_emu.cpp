@@ -852,7 +852,7 @@ int emu_race_model_check(int order, int same_wave) {
 // signals of 2^logn points, x, X as int32 pairs, one emulated workgroup of
 // nthr threads per transform with tracked heap buffers, input and output.
 // Returns the races found, or a negative code.
-int emu_fixed(const int32_t* x, int32_t* X, int logn, int64_t batch, int nthr) {
+int emu_fixed(const int32_t* x, int32_t* X, int logn, int64_t batch, int nthr, int fuse2) {
   if (logn < 1 || logn > 16 || batch < 1 || nthr < 1) return -1;
   const int64_t N = (int64_t)1 << logn;
   std::vector<int> H((size_t)std::max<int64_t>(N / 4, 2)), shift(32);
@@ -869,9 +869,9 @@ int emu_fixed(const int32_t* x, int32_t* X, int logn, int64_t batch, int nthr) {
     // on the GPU
     run_workgroup(nthr, tr, [&](int tid, auto sync, auto wsync) {
       if (nthr <= 64)
-        qftk::fx::transform(xi, Xo, B0, B1, logn, tab, tid, nthr, wsync);
+        qftk::fx::transform(xi, Xo, B0, B1, logn, tab, tid, nthr, wsync, fuse2 != 0);
       else
-        qftk::fx::transform(xi, Xo, B0, B1, logn, tab, tid, nthr, sync);
+        qftk::fx::transform(xi, Xo, B0, B1, logn, tab, tid, nthr, sync, fuse2 != 0);
     });
     if (tr.oob) return -100;
     races += tr.races;

@@ -422,10 +422,11 @@ def _rdft_emu_ref(x):
 @pytest.mark.parametrize("logn", list(range(1, 12)) + [13])
 def test_fixed_point_emulated(emu, logn):
     """The fixed-point kernel body (qft_fixed.hpp) run on the CPU with the
-    library's threads per transform (and with 64 or 256): bit-identical to the
-    integer oracle, including inputs that overflow (two's complement wrap), and
-    race free.  With at most 64 threads the passes are ordered by wavefront
-    syncs only, as the GPU runs transforms of up to 2^8 points."""
+    library's threads per transform (and with 64 or 256), forward rounds one or
+    two per pass: bit-identical to the integer oracle, including inputs that
+    overflow (two's complement wrap), and race free.  With at most 64 threads
+    the passes are ordered by wavefront syncs only, as the GPU runs transforms
+    of up to 2^8 points."""
     from oracle import qft_fixed as F
     N = 1 << logn
     # the GPU's threads per transform: N/4 within [64, 1024], and for N < 2^12
@@ -436,12 +437,13 @@ def test_fixed_point_emulated(emu, logn):
         g = min(g, 1024 // t)
     rng = np.random.default_rng(900 + logn)
     for nthr in sorted({g, 64 if logn <= 9 else 256}):
-        for lim in (1 << (28 - logn), 1 << 31):
-            x = rng.integers(-lim, lim, (2, N, 2)).astype(np.int32)
-            X = np.zeros_like(x)
-            races = emu.emu_fixed(x.ctypes.data, X.ctypes.data, logn, 2, nthr)
-            assert races == 0, nthr
-            assert np.array_equal(X.astype(np.int64), F.cdft_fixed(x)), nthr
+        for fuse2 in (0, 1):
+            for lim in (1 << (28 - logn), 1 << 31):
+                x = rng.integers(-lim, lim, (2, N, 2)).astype(np.int32)
+                X = np.zeros_like(x)
+                races = emu.emu_fixed(x.ctypes.data, X.ctypes.data, logn, 2, nthr, fuse2)
+                assert races == 0, (nthr, fuse2)
+                assert np.array_equal(X.astype(np.int64), F.cdft_fixed(x)), (nthr, fuse2)
 
 
 def test_fixed_point_table_matches_oracle(emu):
