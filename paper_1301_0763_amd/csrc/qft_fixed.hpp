@@ -14,16 +14,19 @@
 //
 // Work layout: the heap layout of qft_device.hpp (sides of N/2 cells, the
 // DCT-II / DST-II block of periodization P at cells [P/4, P/2) of its side,
-// c(0) in cell 0, c(N/2) in cell N/2), one workgroup per transform, one
-// round or chain level per pass:
+// c(0) in cell 0, c(N/2) in cell N/2), one workgroup per transform (or a
+// group of its threads), one round or chain level per pass:
 //   fold             x -> c, d in heap order
-//   forward rounds   S = N/4 .. 2, in place on closed quads of cells
-//   backward rounds  S = 2 .. N/4, from one buffer into the other
+//   forward rounds   S = N/4 .. 2, in place on closed quads of cells (two
+//                    rounds per pass on closed groups of eight, fwd_round2,
+//                    where the caller asks for it)
+//   backward rounds  S = 2 .. N/4, from one buffer into the other, an item per
+//                    pair of output cells
 //   chain levels     P = 2 .. N, in place on closed groups
 //   combine          X(k), X(N-k) from the DCT cell k and the DST cell k
 // The buffers live in LDS (N <= 2^12) or in global scratch (2N cells per
-// transform).  This path is written for exactness and simplicity, not speed:
-// it takes one barrier per round and level (a wavefront's for N <= 2^8).
+// transform).  This path is written for exactness first: it takes one barrier
+// per pass (a wavefront's ordering where one wavefront holds the transform).
 #pragma once
 
 #include <hip/hip_runtime.h>
