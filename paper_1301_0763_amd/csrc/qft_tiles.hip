@@ -27,8 +27,8 @@
 
 namespace qftk {
 
-// The uniform tile kernel's forward rounds: one code path for both sides
-// (16 cells per thread), else a branch between the sides' own code.
+// The uniform and real-input tile kernels' forward rounds: one code path for
+// both sides (16 cells per thread), else a branch between the sides' own code.
 constexpr bool tile_sign_flip(int logn, int tl) {
   return tile_threads_one(logn, tl) == (1 << tl) / 16;
 }
@@ -183,8 +183,8 @@ __global__ __launch_bounds__(tile_threads_one(LOGN, TL)) void tile_kernel_r(Real
   if constexpr (KIND == 0) {
     using E = typename Store<DT>::T;
     const RealPairIO<DT, LOGN> io{(const R*)a.in0 + r0 * n, (E*)a.out0 + r0 * (h + 1), rows - r0};
-    tile_body_s<LOGN, T, tile_threads_one(LOGN, TL), kWave>(io, W, count, sec, (int)threadIdx.x,
-                                                            DevSync{}, DevWaveSync{});
+    tile_body_s<LOGN, T, tile_threads_one(LOGN, TL), kWave, tile_sign_flip(LOGN, TL)>(
+        io, W, count, sec, (int)threadIdx.x, DevSync{}, DevWaveSync{});
   } else {
     const R* c = (const R*)a.in0;
     const R* d = (const R*)a.in1;
@@ -193,8 +193,8 @@ __global__ __launch_bounds__(tile_threads_one(LOGN, TL)) void tile_kernel_r(Real
     const DctDstIO<DT, LOGN> io{c ? c + r0 * (h + 1) : nullptr, d ? d + r0 * (h - 1) : nullptr,
                                 C ? C + r0 * (h + 1) : nullptr, S ? S + r0 * (h - 1) : nullptr,
                                 rows - r0};
-    tile_body_s<LOGN, T, tile_threads_one(LOGN, TL), kWave>(io, W, count, sec, (int)threadIdx.x,
-                                                            DevSync{}, DevWaveSync{});
+    tile_body_s<LOGN, T, tile_threads_one(LOGN, TL), kWave, tile_sign_flip(LOGN, TL)>(
+        io, W, count, sec, (int)threadIdx.x, DevSync{}, DevWaveSync{});
   }
 }
 

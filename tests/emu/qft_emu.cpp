@@ -339,6 +339,7 @@ int tile_real_impl(int64_t rows, const void* in0, const void* in1, void* out0, v
   using E = typename qftk::Store<DT>::T;
   constexpr int TL = LOGN <= 10 ? 10 : LOGN;
   constexpr int NT = emu_tile_threads<LOGN, TL>(false);
+  constexpr bool SF = NT == (1 << TL) / 16;  // as the GPU's real-input kernel
   constexpr int T = 1 << (TL - LOGN);
   const int slots = (int)((rows + 1) / 2);
   if (rows < 1 || slots > T) return -2;
@@ -349,10 +350,10 @@ int tile_real_impl(int64_t rows, const void* in0, const void* in1, void* out0, v
   run_workgroup(NT, tr, [&](int tid, auto sync, auto wsync) {
     if constexpr (KIND == 0) {
       const qftk::RealPairIO<DT, LOGN> io{(const R*)in0, (E*)out0, rows};
-      qftk::tile_body_s<LOGN, T, NT, 64>(io, W, slots, sec, tid, sync, wsync);
+      qftk::tile_body_s<LOGN, T, NT, 64, SF>(io, W, slots, sec, tid, sync, wsync);
     } else {
       const qftk::DctDstIO<DT, LOGN> io{(const R*)in0, (const R*)in1, (R*)out0, (R*)out1, rows};
-      qftk::tile_body_s<LOGN, T, NT, 64>(io, W, slots, sec, tid, sync, wsync);
+      qftk::tile_body_s<LOGN, T, NT, 64, SF>(io, W, slots, sec, tid, sync, wsync);
     }
   });
   return tr.oob ? -100 : (int)tr.races;
