@@ -69,11 +69,11 @@ __global__ __launch_bounds__(1024) void fixed_kernel(const int2* x, int2* X, int
   int2* b0 = LDS ? lds + 2 * N * k : scratch + 2 * N * t;
   int2* b1 = b0 + N;
   const int tt = t < batch ? lt : (int)N;
-  // G <= 64 (N <= 2^8): each transform's threads and LDS buffers belong to
-  // one wavefront, so its passes are ordered by the wavefront alone
   // two forward rounds per pass from N = 2^12 on (measured faster there,
   // slower for the smaller transforms, whose passes then have too few items)
   const bool fuse2 = logn >= 12;
+  // G <= 64 (N <= 2^8): each transform's threads and LDS buffers belong to
+  // one wavefront, so its passes are ordered by the wavefront alone
   if (LDS && G <= kWave)
     fx::transform(SwapIn<SWAP>{x + N * t}, SwapOut<SWAP>{X + N * t}, b0, b1, logn,
                   fx::Table{H, shift}, tt, G, DevWaveSync{}, fuse2);
